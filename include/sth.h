@@ -1,0 +1,200 @@
+/*
+ * sth.h -- C-ABI of the MI355X Sternheimer library.
+ *
+ * The library solves, for a periodic Kohn-Sham system in a plane-wave basis
+ * (Gamma point), the linear-response (Sternheimer) equations
+ *
+ *     P_c (H - eps_v) P_c dpsi_jv = -P_c dV_j psi_v ,   P_c = 1 - sum_v |psi_v><psi_v|
+ *
+ * for every perturbation dV_j and valence band v of a request, by batched
+ * preconditioned conjugate gradient, and returns the density response
+ *
+ *     dn_j(r) = f_s sum_v [psi_v^*(r) dpsi_jv(r) + c.c.]      ( = chi0 . dV_j )
+ *
+ * (paper: Section 3, the Sternheimer equation and the density-response
+ * equation; P_c = 1 - P_v by completeness; the equations are independent per
+ * perturbation, spin and orbital, which the library exploits as batch
+ * parallelism).  H = T + V_loc + V_NL is applied by the dual-space technique
+ * with sphere-pruned FFTs (Section 4.1) and Kleinman-Bylander projectors.
+ *
+ * Units: Hartree atomic units.  Cell: cubic, edge L (bohr), FFT grid n^3.
+ * Conventions shared by every call:
+ *   - plane waves G = (2 pi / L) m for integer Miller indices m; the caller's
+ *     order of the npw indices defines the order of every coefficient array;
+ *   - psi(r) = Omega^{-1/2} sum_G c(G) exp(i G.r), Omega = L^3;
+ *   - real-space arrays are n^3 doubles in C order, element (i0, i1, i2) at
+ *     r = (i0, i1, i2) L / n, index (i0 n + i1) n + i2;
+ *   - complex arrays are interleaved (re, im) doubles (complex128);
+ *   - ptr_kind STH_PTR_HOST: pageable or pinned host memory;
+ *     STH_PTR_DEVICE: device memory of the context's GPU (e.g. a torch
+ *     tensor's data_ptr()); device inputs are read after all work already
+ *     queued on `stream` (a hipStream_t, NULL = default stream), device
+ *     outputs are complete before later work on `stream` starts.
+ *   - inputs are copied before the call returns; the caller may free them.
+ *
+ * Errors: every call returns STH_OK (0) or a negative sth_status and sets a
+ * thread-local message (sth_last_error).  No exception crosses the ABI.
+ * A solve that does not converge is NOT a call error: it is reported per
+ * solve by sth_fetch_stats.  All calls are thread-safe.
+ */
+#ifndef STH_H
+#define STH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sth_ctx sth_ctx;
+
+typedef enum {
+  STH_OK = 0,
+  STH_E_INVALID = -1,   /* bad argument (message says which) */
+  STH_E_NOMEM = -2,     /* does not fit the context's HBM budget */
+  STH_E_AGAIN = -3,     /* admission queue full, retry later */
+  STH_E_NOT_READY = -4, /* ticket not finished */
+  STH_E_DEVICE = -5,    /* HIP runtime error */
+  STH_E_NOT_FOUND = -6, /* unknown system id or ticket */
+  STH_E_INTERNAL = -7
+} sth_status;
+
+enum { STH_PTR_HOST = 0, STH_PTR_DEVICE = 1 };
+
+/* Precision of a solve.  STH_FP64: everything in FP64.  STH_MIXED: FP32
+ * FFTs / H.psi inside the CG iterations with FP64 recurrences, residuals and
+ * P_c; the returned solution always meets tol on the true FP64 residual
+ * (paper, Section 4.3 and 5.1: FP32 FFTs and communication, FP64 elsewhere). */
+enum { STH_FP64 = 0, STH_MIXED = 1 };
+
+/* Per-solve status codes returned by sth_fetch_stats. */
+enum {
+  STH_SOLVE_CONVERGED = 0,
+  STH_SOLVE_MAXIT = 1,     /* maxit reached; solution is the last iterate */
+  STH_SOLVE_BREAKDOWN = 2, /* Re<p, A p> <= 0 (operator not positive definite) */
+  STH_SOLVE_NAN = 3        /* non-finite value in the right-hand side or iterates */
+};
+
+typedef struct {
+  int device;               /* HIP device ordinal */
+  size_t hbm_budget_bytes;  /* device memory the context may use; 0 = 90% of free */
+  int max_slots;            /* solves in flight per system; 0 = derived from the budget */
+  int check_every;          /* CG iterations between convergence polls; 0 = default (2) */
+} sth_config;
+
+typedef struct {
+  double L;                 /* cubic cell edge (bohr) */
+  int n;                    /* FFT grid points per axis: 24, 48, 72 or 96 */
+  int npw;                  /* plane waves in the wave-function sphere */
+  const int32_t* miller;    /* [npw][3]; host memory always; must satisfy 4 max|m_i| + 1 <= n */
+  const double* vloc_r;     /* [n^3] local potential (Ha) */
+  int nproj;                /* Kleinman-Bylander projectors (may be 0) */
+  const double* beta;       /* complex128 [nproj][npw] */
+  const double* dij;        /* [nproj] KB coefficients (Ha), diagonal */
+  int nv;                   /* valence bands (0 allowed only for sth_valence) */
+  const double* psi_v;      /* complex128 [nv][npw], orthonormal */
+  const double* eps_v;      /* [nv] band energies (Ha), ascending */
+  double spin_factor;       /* f_s in dn; 2.0 for a spin-unpolarised system */
+  int ptr_kind;             /* of vloc_r, beta, dij, psi_v, eps_v */
+} sth_system_desc;
+
+typedef struct {
+  double tol;               /* relative true residual ||b - A x|| / ||b|| to reach */
+  int maxit;                /* CG iterations per solve (0 = 1000) */
+  int precision;            /* STH_FP64 or STH_MIXED */
+  int want_dpsi;            /* keep dpsi for sth_fetch_dpsi */
+} sth_solve_opts;
+
+typedef struct {
+  int state;                /* 0 queued, 1 running, 2 done */
+  int n_total;              /* solves in the ticket (npert * nband) */
+  int n_finished;           /* solves retired so far */
+  int n_converged;          /* of which converged */
+  double max_rel_resid;     /* largest final true relative residual so far */
+  double t_submit, t_start, t_done;   /* seconds on the library's monotonic clock */
+  long long cg_iterations;  /* sum of CG iterations over finished solves */
+  long long op_applications;/* operator applications incl. true-residual checks */
+} sth_ticket_info;
+
+/* Creates a context on cfg->device (cfg may be NULL for defaults).  Starts the
+ * context's solve-server thread.  *out is owned by the caller until sth_destroy. */
+sth_status sth_create(const sth_config* cfg, sth_ctx** out);
+
+/* Waits for running work, frees every device allocation, joins the server. */
+sth_status sth_destroy(sth_ctx* ctx);
+
+/* Uploads one system (paper, Section 4: data is copied to the GPU once and
+ * stays resident): validates the sphere (no duplicates, alias-free grid),
+ * builds the z-stick maps, keeps V_loc, the projectors, psi_v, eps_v and
+ * psi_v(r) on the device.  Fails with STH_E_NOMEM if the resident data plus
+ * a minimal slot pool does not fit the budget.  nv >= 1 is required. */
+sth_status sth_set_system(sth_ctx* ctx, const sth_system_desc* desc, void* stream,
+                          int32_t* system_id);
+
+/* Frees a system; its unfinished tickets fail with STH_E_NOT_FOUND afterwards. */
+sth_status sth_release_system(sth_ctx* ctx, int32_t system_id);
+
+/* out = H c for nvec vectors (complex128 [nvec][npw] in the caller's order);
+ * H = T + V_loc + V_NL without shift or projector (dual-space FFT route,
+ * Section 4.1).  Synchronous with respect to `stream`. */
+sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* in,
+                       double* out, int ptr_kind, void* stream);
+
+/* Lowest nbands eigenpairs of H for a system description whose psi_v / eps_v
+ * are ignored (nv may be 0), by block LOBPCG on the device with FP64
+ * Rayleigh-Ritz.  eps_out [nbands], psi_out complex128 [nbands][npw] (caller
+ * order), both in `out_ptr_kind` memory.  Converged when every residual
+ * ||H x - theta x|| <= tol.  *iters and *max_resid report the run. */
+sth_status sth_valence(sth_ctx* ctx, const sth_system_desc* desc, int nbands, double tol,
+                       int maxit, double* eps_out, double* psi_out, int out_ptr_kind,
+                       double* max_resid, int* iters);
+
+/* Queues npert x nband solves: dV_j = dv_r[j] (real [npert][n^3]) for every
+ * band index in bands[0..nband) (0 <= band < nv, no duplicates).  Returns at
+ * once with a ticket; the server admits the request when its perturbations
+ * fit the budget.  STH_E_NOMEM if it can never fit, STH_E_AGAIN if the queue
+ * is full. */
+sth_status sth_submit_solves(sth_ctx* ctx, int32_t system_id, int npert, const double* dv_r,
+                             int nband, const int32_t* bands, const sth_solve_opts* opts,
+                             int ptr_kind, void* stream, uint64_t* ticket);
+
+/* Non-blocking progress of a ticket. */
+sth_status sth_poll(sth_ctx* ctx, uint64_t ticket, sth_ticket_info* info);
+
+/* Blocks until the ticket is done or timeout_s elapses (STH_E_NOT_READY). */
+sth_status sth_wait(sth_ctx* ctx, uint64_t ticket, double timeout_s);
+
+/* dn_j(r) for the ticket's perturbations: real [npert][n^3]. */
+sth_status sth_fetch_drho(sth_ctx* ctx, uint64_t ticket, double* drho, int ptr_kind,
+                          void* stream);
+
+/* dpsi_jv: complex128 [npert][nband][npw] in the caller's coefficient order
+ * (requires want_dpsi). */
+sth_status sth_fetch_dpsi(sth_ctx* ctx, uint64_t ticket, double* dpsi, int ptr_kind,
+                          void* stream);
+
+/* Per-solve results, each array [npert][nband] in host memory (any may be NULL):
+ * CG iterations, final true relative residual, STH_SOLVE_* status, latency
+ * from admission of the solve to its retirement (s). */
+sth_status sth_fetch_stats(sth_ctx* ctx, uint64_t ticket, int32_t* iters, double* rel_resid,
+                           int32_t* status, double* latency_s);
+
+/* Rayleigh-Ritz of chi0 in span{dV_j} of a finished ticket (paper, Section 3:
+ * the first Rayleigh-Ritz step of the projective eigendecomposition):
+ * M_ij = (Omega/n^3) sum_r dV_i dn_j, S_ij = (Omega/n^3) sum_r dV_i dV_j and the
+ * ascending eigenvalues of (sym(M), S), computed in FP64 on the device.  Host
+ * arrays M, S [npert][npert] and lambda [npert]; any may be NULL. */
+sth_status sth_chi0_block(sth_ctx* ctx, uint64_t ticket, double* M, double* S, double* lambda);
+
+/* Frees a finished ticket's device results. */
+sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sth_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STH_H */

@@ -1,0 +1,288 @@
+"""ctypes binding of libsth.so (the C-ABI declared in include/sth.h).
+
+Argument marshalling only: every step of the Sternheimer path runs in the HIP
+library.  Arrays may be numpy arrays (host) or torch CUDA tensors (device
+pointers, ordered against torch's current stream).  The library must have
+been built (``paper_2203_05623_amd.build.build()``); importing this module
+without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsth.so")
+
+STH_OK, STH_E_INVALID, STH_E_NOMEM, STH_E_AGAIN, STH_E_NOT_READY = 0, -1, -2, -3, -4
+STH_E_DEVICE, STH_E_NOT_FOUND, STH_E_INTERNAL = -5, -6, -7
+STH_PTR_HOST, STH_PTR_DEVICE = 0, 1
+STH_FP64, STH_MIXED = 0, 1
+SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
+
+EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
+           "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
+           "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
+           "sth_last_error"]
+
+
+class sth_config(C.Structure):
+    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int),
+                ("check_every", C.c_int)]
+
+
+class sth_system_desc(C.Structure):
+    _fields_ = [("L", C.c_double), ("n", C.c_int), ("npw", C.c_int),
+                ("miller", C.POINTER(C.c_int32)), ("vloc_r", C.c_void_p), ("nproj", C.c_int),
+                ("beta", C.c_void_p), ("dij", C.c_void_p), ("nv", C.c_int), ("psi_v", C.c_void_p),
+                ("eps_v", C.c_void_p), ("spin_factor", C.c_double), ("ptr_kind", C.c_int)]
+
+
+class sth_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("precision", C.c_int),
+                ("want_dpsi", C.c_int)]
+
+
+class sth_ticket_info(C.Structure):
+    _fields_ = [("state", C.c_int), ("n_total", C.c_int), ("n_finished", C.c_int),
+                ("n_converged", C.c_int), ("max_rel_resid", C.c_double),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("cg_iterations", C.c_longlong), ("op_applications", C.c_longlong)]
+
+
+class SthError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2203_05623_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, dbl, u64 = C.c_void_p, C.c_int32, C.c_double, C.c_uint64
+    sig = {
+        "sth_create": [C.POINTER(sth_config), C.POINTER(vp)],
+        "sth_destroy": [vp],
+        "sth_set_system": [vp, C.POINTER(sth_system_desc), vp, C.POINTER(i32)],
+        "sth_release_system": [vp, i32],
+        "sth_apply_h": [vp, i32, C.c_int, vp, vp, C.c_int, vp],
+        "sth_valence": [vp, C.POINTER(sth_system_desc), C.c_int, dbl, C.c_int, vp, vp, C.c_int,
+                        C.POINTER(dbl), C.POINTER(C.c_int)],
+        "sth_submit_solves": [vp, i32, C.c_int, vp, C.c_int, C.POINTER(i32),
+                              C.POINTER(sth_solve_opts), C.c_int, vp, C.POINTER(u64)],
+        "sth_poll": [vp, u64, C.POINTER(sth_ticket_info)],
+        "sth_wait": [vp, u64, dbl],
+        "sth_fetch_drho": [vp, u64, vp, C.c_int, vp],
+        "sth_fetch_dpsi": [vp, u64, vp, C.c_int, vp],
+        "sth_fetch_stats": [vp, u64, vp, vp, vp, vp],
+        "sth_chi0_block": [vp, u64, vp, vp, vp],
+        "sth_release_ticket": [vp, u64],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.sth_last_error.argtypes = []
+    lib.sth_last_error.restype = C.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _check(code):
+    if code != STH_OK:
+        raise SthError(code, lib().sth_last_error().decode())
+
+
+# ------------------------------------------------------------------ marshalling helpers
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype):
+    """(pointer, ptr_kind, keepalive) of a numpy array or a torch tensor."""
+    if a is None:
+        return None, STH_PTR_HOST, None
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if a.is_cuda:
+            return a.data_ptr(), STH_PTR_DEVICE, a
+        a = a.numpy()
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, STH_PTR_HOST, arr
+
+
+def _stream(a=None):
+    if a is not None and _is_torch(a) and a.is_cuda:
+        import torch
+        return torch.cuda.current_stream(a.device).cuda_stream
+    return None
+
+
+def _c128_as_f64(a):
+    if _is_torch(a):
+        import torch
+        return torch.view_as_real(a) if a.is_complex() else a
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+# ------------------------------------------------------------------ C-ABI functions
+def sth_create(device=0, hbm_budget_bytes=0, max_slots=0, check_every=0):
+    cfg = sth_config(device, hbm_budget_bytes, max_slots, check_every)
+    h = C.c_void_p()
+    _check(lib().sth_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def sth_destroy(ctx):
+    _check(lib().sth_destroy(ctx))
+
+
+def _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor):
+    miller = np.ascontiguousarray(miller, dtype=np.int32).reshape(-1, 3)
+    npw = len(miller)
+    keep = [miller]
+    kinds = set()
+
+    def p(a, dt):
+        ptr, kind, k = _ptr(a, dt)
+        keep.append(k)
+        if a is not None:
+            kinds.add(kind)
+        return ptr
+
+    nproj = 0 if beta is None else int(beta.shape[0])
+    nv = 0 if psi_v is None else int(psi_v.shape[0])
+    d = sth_system_desc(
+        L=float(L), n=int(n), npw=npw, miller=miller.ctypes.data_as(C.POINTER(C.c_int32)),
+        vloc_r=p(vloc_r, np.float64), nproj=nproj,
+        beta=p(None if beta is None else _c128_as_f64(beta), np.complex128),
+        dij=p(dij, np.float64), nv=nv,
+        psi_v=p(None if psi_v is None else _c128_as_f64(psi_v), np.complex128),
+        eps_v=p(eps_v, np.float64), spin_factor=float(spin_factor), ptr_kind=STH_PTR_HOST)
+    if len(kinds) > 1:
+        raise ValueError("system arrays must all be host arrays or all device tensors")
+    d.ptr_kind = kinds.pop() if kinds else STH_PTR_HOST
+    return d, keep
+
+
+def sth_set_system(ctx, L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor=2.0):
+    d, keep = _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor)
+    sid = C.c_int32()
+    _check(lib().sth_set_system(ctx, C.byref(d), _stream(vloc_r), C.byref(sid)))
+    del keep
+    return sid.value
+
+
+def sth_release_system(ctx, system_id):
+    _check(lib().sth_release_system(ctx, system_id))
+
+
+def sth_apply_h(ctx, system_id, c, out=None):
+    """H c for c complex [nvec, npw] (numpy or torch); returns out."""
+    nvec = c.shape[0]
+    if out is None:
+        out = np.empty_like(np.asarray(c, dtype=np.complex128)) if not _is_torch(c) else c.clone()
+    pin, kin, k1 = _ptr(_c128_as_f64(c), np.complex128)
+    pout, kout, k2 = _ptr(_c128_as_f64(out), np.complex128)
+    if kin != kout:
+        raise ValueError("in and out must live on the same side")
+    _check(lib().sth_apply_h(ctx, system_id, nvec, pin, pout, kin, _stream(c)))
+    return out
+
+
+def sth_valence(ctx, L, n, miller, vloc_r, beta, dij, nbands, tol=1e-10, maxit=0,
+                spin_factor=2.0):
+    d, keep = _desc(L, n, miller, vloc_r, beta, dij, None, None, spin_factor)
+    npw = d.npw
+    eps = np.empty(nbands)
+    psi = np.empty((nbands, npw), np.complex128)
+    res = C.c_double()
+    its = C.c_int()
+    _check(lib().sth_valence(ctx, C.byref(d), nbands, tol, maxit, eps.ctypes.data,
+                             psi.ctypes.data, STH_PTR_HOST, C.byref(res), C.byref(its)))
+    del keep
+    return eps, psi, res.value, its.value
+
+
+def sth_submit_solves(ctx, system_id, dv_r, bands, tol=1e-10, maxit=0, precision=STH_FP64,
+                      want_dpsi=False):
+    npert = int(dv_r.shape[0])
+    bands = np.ascontiguousarray(bands, dtype=np.int32)
+    pdv, kind, keep = _ptr(dv_r, np.float64)
+    opts = sth_solve_opts(float(tol), int(maxit), int(precision), int(bool(want_dpsi)))
+    t = C.c_uint64()
+    _check(lib().sth_submit_solves(ctx, system_id, npert, pdv, len(bands),
+                                   bands.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(opts),
+                                   kind, _stream(dv_r), C.byref(t)))
+    del keep
+    return t.value
+
+
+def sth_poll(ctx, ticket):
+    info = sth_ticket_info()
+    _check(lib().sth_poll(ctx, ticket, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in sth_ticket_info._fields_}
+
+
+def sth_wait(ctx, ticket, timeout_s=1e9):
+    code = lib().sth_wait(ctx, ticket, float(timeout_s))
+    if code == STH_E_NOT_READY:
+        return False
+    _check(code)
+    return True
+
+
+def sth_fetch_drho(ctx, ticket, out):
+    p, kind, keep = _ptr(out, np.float64)
+    if keep is not out and not _is_torch(out):
+        raise ValueError("out must be a C-contiguous float64 array")
+    _check(lib().sth_fetch_drho(ctx, ticket, p, kind, _stream(out)))
+    return out
+
+
+def sth_fetch_dpsi(ctx, ticket, out):
+    o = _c128_as_f64(out)
+    p, kind, keep = _ptr(o, np.complex128)
+    if not _is_torch(out) and keep is not out:
+        raise ValueError("out must be a C-contiguous complex128 array")
+    _check(lib().sth_fetch_dpsi(ctx, ticket, p, kind, _stream(out)))
+    return out
+
+
+def sth_fetch_stats(ctx, ticket, n):
+    iters = np.empty(n, np.int32)
+    resid = np.empty(n)
+    status = np.empty(n, np.int32)
+    lat = np.empty(n)
+    _check(lib().sth_fetch_stats(ctx, ticket, iters.ctypes.data, resid.ctypes.data,
+                                 status.ctypes.data, lat.ctypes.data))
+    return iters, resid, status, lat
+
+
+def sth_chi0_block(ctx, ticket, npert):
+    M = np.empty((npert, npert))
+    S = np.empty((npert, npert))
+    lam = np.empty(npert)
+    _check(lib().sth_chi0_block(ctx, ticket, M.ctypes.data, S.ctypes.data, lam.ctypes.data))
+    return M, S, lam
+
+
+def sth_release_ticket(ctx, ticket):
+    _check(lib().sth_release_ticket(ctx, ticket))
+
+
+def sth_last_error():
+    return lib().sth_last_error().decode()

@@ -1,0 +1,213 @@
+// Host side of the Sternheimer library: resident systems, the solve server
+// and its slot pool.  One process, one device per context.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "errors.hpp"
+#include "kernels.hpp"
+
+namespace sth {
+
+double now_s();
+
+// Owning device allocation, charged against the context's HBM budget.
+class Budget;
+class DevMem {
+ public:
+  DevMem() = default;
+  DevMem(Budget* b, size_t bytes);
+  ~DevMem();
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept { *this = std::move(o); }
+  DevMem& operator=(DevMem&& o) noexcept;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p_); }
+  size_t bytes() const { return n_; }
+  void zero(hipStream_t st);
+
+ private:
+  void release();
+  void* p_ = nullptr;
+  size_t n_ = 0;
+  Budget* b_ = nullptr;
+};
+
+class Budget {
+ public:
+  explicit Budget(size_t limit) : limit_(limit) {}
+  void set_limit(size_t limit) { limit_ = limit; }
+  bool fits(size_t bytes) const { return used_ + bytes <= limit_; }
+  void charge(size_t bytes);   // throws STH_E_NOMEM
+  void credit(size_t bytes) { used_ -= bytes; }
+  size_t used() const { return used_; }
+  size_t limit() const { return limit_; }
+
+ private:
+  std::atomic<size_t> used_{0};
+  size_t limit_;
+};
+
+// Pinned host staging.
+class HostMem {
+ public:
+  HostMem() = default;
+  explicit HostMem(size_t bytes);
+  ~HostMem();
+  HostMem(const HostMem&) = delete;
+  HostMem& operator=(const HostMem&) = delete;
+  HostMem& operator=(HostMem&& o) noexcept {
+    std::swap(p_, o.p_);
+    return *this;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p_); }
+
+ private:
+  void* p_ = nullptr;
+};
+
+// Dense Hermitian eigensolver on the device (Jacobi): A (n x n, row-major,
+// destroyed), ascending eigenvalues to host w, eigenvectors as columns of V.
+void eig_hermitian_device(Budget* b, z64* A, int n, double* w, z64* V, hipStream_t st);
+void small_mm_device(const z64* A, const z64* B, z64* C, int n, bool ah, hipStream_t st);
+void scale_cols_device(z64* V, int n, const double* s_dev, hipStream_t st);
+// Ascending eigenvalues of the pencil (sym(M), S) of host matrices, on the device.
+void gen_eig_device(Budget* b, const std::vector<double>& M, const std::vector<double>& S, int n,
+                    double* lam, hipStream_t st);
+
+struct Request;
+
+struct SlotHost {
+  Request* req = nullptr;   // owner of the solve in this slot (null = free)
+  int solve = -1;           // j * nband + band index within the request
+  double t_admit = 0.0;
+  int restarts = 0;
+};
+
+struct System {
+  int id = 0;
+  int N = 0, npw = 0, nst = 0, nrow = 0, nv = 0, nproj = 0, M = 0;
+  double L = 0.0, omega = 0.0, fs = 2.0, alpha_pv = 0.0;
+  GridDev g;
+  DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_kin, d_tw64, d_tw32, d_perm;
+  DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
+  DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
+  DevMem d_vloc;       // [N^3] double
+  DevMem d_psir;       // [nv][N^3] z64, psi_v(r) without Omega^{-1/2}
+  DevMem d_eps_band;   // [nv]
+  std::vector<double> eps, ekin;   // per band
+  std::vector<int> perm;           // caller index -> internal index
+
+  // slot pool
+  int nslots = 0;
+  int kchunk = 2048, nsplit = 1, ntile = 1, nchunk = 1;
+  DevMem d_x, d_r, d_p, d_q, d_b, d_sticks, d_part, d_C, d_dots, d_part2;
+  DevMem d_ss_d, d_ss_i;     // SlotState doubles [7][nslots], ints [2][nslots]
+  DevMem d_potptr;           // [nslots] const double*
+  DevMem d_lists;            // index arena for slot lists
+  HostMem h_potptr, h_eps, h_ekin, h_lists, h_status, h_iters, h_rn2, h_bn2;
+  SlotState ss;
+  std::vector<SlotHost> slots;
+  int lists_used = 0;
+  DevMem d_drho_sticks;      // [nband_max][N][nst] z64 scratch of the density response
+  int drho_nb = 0;
+
+  std::deque<std::shared_ptr<Request>> waiting;   // submitted, not admitted
+  std::vector<std::shared_ptr<Request>> running;  // admitted, unfinished
+
+  VecSet<z64> vec(const DevMem& m) const { return {m.as<z64>(), (long long)npw}; }
+  VecSet<const z64> cvec(const DevMem& m) const { return {m.as<const z64>(), (long long)npw}; }
+  const z64* W() const { return d_W.as<const z64>(); }
+  const z64* beta() const { return d_W.as<const z64>() + (size_t)nv * npw; }
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  int sys_id = 0;
+  System* sys = nullptr;
+  int npert = 0, nband = 0;
+  std::vector<int> bands;
+  double tol = 1e-10;
+  int maxit = 1000, precision = 0, want_dpsi = 0;
+  std::vector<double> dv_host;       // until admission
+  DevMem d_dv;                       // [npert][N^3]
+  DevMem d_dpsi;                     // [npert][nband][npw] internal order
+  DevMem d_drho;                     // [npert][N^3]
+  DevMem d_bands;                    // [nband]
+  // progress (guarded by the context mutex)
+  int state = 0;                     // 0 queued, 1 running, 2 done, 3 failed
+  int next = 0;                      // next solve to assign
+  int n_finished = 0, n_converged = 0;
+  std::vector<int> pert_left;        // unfinished bands per perturbation
+  std::vector<int> drho_pending;     // perturbations whose bands are all finished
+  int n_drho_done = 0;
+  double max_resid = 0.0, t_submit = 0.0, t_start = 0.0, t_done = 0.0;
+  long long cg_its = 0, op_apps = 0;
+  std::vector<int> iters, status;
+  std::vector<double> resid, latency;
+  bool failed = false;
+  int fail_code = 0;
+};
+
+class Context {
+ public:
+  Context(const sth_config& cfg);
+  ~Context();
+
+  int set_system(const sth_system_desc& d, hipStream_t user);
+  void release_system(int id);
+  void apply_h(int id, int nvec, const double* in, double* out, int ptr_kind, hipStream_t user);
+  void valence(const sth_system_desc& d, int nbands, double tol, int maxit, double* eps_out,
+               double* psi_out, int ptr_kind, double* max_resid, int* iters);
+  uint64_t submit(int id, int npert, const double* dv, int nband, const int32_t* bands,
+                  const sth_solve_opts& o, int ptr_kind, hipStream_t user);
+  void poll(uint64_t t, sth_ticket_info* info);
+  bool wait(uint64_t t, double timeout);
+  void fetch_drho(uint64_t t, double* out, int ptr_kind, hipStream_t user);
+  void fetch_dpsi(uint64_t t, double* out, int ptr_kind, hipStream_t user);
+  void fetch_stats(uint64_t t, int32_t* iters, double* resid, int32_t* status, double* lat);
+  void chi0_block(uint64_t t, double* M, double* S, double* lam);
+  void release_ticket(uint64_t t);
+
+ private:
+  std::shared_ptr<Request> find(uint64_t t);
+  System& sys(int id);
+  void server_loop();
+  bool step(System& s);                       // one check period; true if work was done
+  void admit(System& s);
+  void refill(System& s);
+  void iterate(System& s, const std::vector<int>& act, int nit);
+  void check_and_retire(System& s, std::vector<int>& act);
+  void finish_drho(System& s);
+  int* upload_list(System& s, const std::vector<int>& v);
+  void apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
+                bool dots);
+  void order_after(hipStream_t user);   // library stream waits for the user's stream
+  void order_before(hipStream_t user);  // user's stream waits for the library stream
+  void alloc_slots(System& s, int nslots);
+
+  int device_;
+  Budget budget_;
+  int max_slots_, check_every_;
+  hipStream_t st_ = nullptr;
+  std::mutex mu_;        // tickets, systems map, request progress
+  std::mutex gpu_mu_;    // serialises device work of API calls and the server
+  std::condition_variable cv_;
+  std::thread server_;
+  bool stop_ = false;
+  std::map<int, std::unique_ptr<System>> systems_;
+  std::map<uint64_t, std::shared_ptr<Request>> tickets_;
+  int next_sys_ = 1;
+  uint64_t next_ticket_ = 1;
+};
+
+}  // namespace sth

@@ -1,0 +1,357 @@
+// Sphere-pruned 3D FFT stages of the dual-space Hamiltonian (paper, Section 4.1:
+// kinetic term in reciprocal space, local potential in real space, only the
+// Fourier components inside the cutoff sphere are kept).
+//
+// A wave function on the sphere is carried through three kernels:
+//   zfft_inv   sphere -> z-sticks: each stick (fixed m1, m2) is a line along
+//              grid axis 0; its run of coefficients is placed at i0 = m0 mod N
+//              and inverse-transformed.  Output layout [i0][stick] so that a
+//              plane (fixed i0) of all sticks is one contiguous row.
+//   plane_*    one workgroup per (vector, i0): the stick values of the plane
+//              are scattered into an N x N LDS tile, inverse-transformed along
+//              i2 (only rows that hold sticks) and i1, multiplied by the real
+//              potential, transformed forward and gathered back.
+//   zfft_fwd   z-sticks -> sphere: forward transform along axis 0, 1/N^3, the
+//              sphere components extracted, kinetic and shift terms fused.
+#include "errors.hpp"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace sth {
+
+namespace {
+
+constexpr int ZTHR = 256;
+
+// sticks per workgroup in the z-stick kernels: 64, halved while the LDS tile
+// would exceed 40 KB
+template <int N, typename T>
+constexpr int zsticks() {
+  return (64 * (N + 1) * int(sizeof(cpx<T>)) > 40960) ? 32 : 64;
+}
+constexpr int PTHR = 256;    // threads of a plane workgroup
+
+template <typename T>
+__device__ inline const cpx<T>* twiddles(const GridDev& g);
+template <>
+__device__ inline const cpx<double>* twiddles<double>(const GridDev& g) { return g.tw64; }
+template <>
+__device__ inline const cpx<float>* twiddles<float>(const GridDev& g) { return g.tw32; }
+
+template <typename T, typename S>
+__device__ inline cpx<T> cvt(const S& v) { return cpx<T>{T(v.x), T(v.y)}; }
+
+template <typename Z>
+struct real_of;
+template <typename T>
+struct real_of<cpx<T>> {
+  using type = T;
+};
+
+// ------------------------------------------------------------------ z sticks
+template <int N, typename T, typename Tin>
+__global__ __launch_bounds__(ZTHR) void k_zfft_inv(GridDev g, VecSet<const Tin> in,
+                                                    VecSet<cpx<T>> sticks, const int* slots) {
+  constexpr int NPAD = N + 1;
+  constexpr int ZS = zsticks<N, T>();
+  __shared__ cpx<T> buf[ZS * NPAD];
+  const int slot = slots[blockIdx.y];
+  const int s0 = blockIdx.x * ZS;
+  const int ns = min(ZS, g.nst - s0);
+  for (int i = threadIdx.x; i < ZS * NPAD; i += ZTHR) buf[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  const Tin* src = in.base + slot * in.stride;
+  const int e0 = g.stick_off[s0], e1 = g.stick_off[s0 + ns];
+  for (int e = e0 + threadIdx.x; e < e1; e += ZTHR) {
+    const int pos = g.elem_pos[e];
+    const int st = pos / N - s0, i0 = pos - (pos / N) * N;
+    buf[st * NPAD + i0] = cvt<T>(src[e]);
+  }
+  __syncthreads();
+  RadixPlan<N>::template fft<T, +1, ZTHR, ZS>::run(
+      buf, ns, 1, [](int f) { return f * NPAD; }, twiddles<T>(g));
+  cpx<T>* dst = sticks.base + slot * sticks.stride;
+  for (int t = threadIdx.x; t < N * ns; t += ZTHR) {
+    const int i0 = t / ns, st = t - i0 * ns;
+    dst[(long long)i0 * g.nst + s0 + st] = buf[st * NPAD + i0];
+  }
+}
+
+template <int N, typename T, typename Tout>
+__global__ __launch_bounds__(ZTHR) void k_zfft_fwd(GridDev g, VecSet<const cpx<T>> sticks,
+                                                    VecSet<Tout> out, const int* slots,
+                                                    int mode, VecSet<const Tout> pin,
+                                                    const double* eps_slot) {
+  constexpr int NPAD = N + 1;
+  constexpr int ZS = zsticks<N, T>();
+  __shared__ cpx<T> buf[ZS * NPAD];
+  const int slot = slots[blockIdx.y];
+  const int s0 = blockIdx.x * ZS;
+  const int ns = min(ZS, g.nst - s0);
+  const cpx<T>* src = sticks.base + slot * sticks.stride;
+  for (int t = threadIdx.x; t < N * ns; t += ZTHR) {
+    const int i0 = t / ns, st = t - i0 * ns;
+    buf[st * NPAD + i0] = src[(long long)i0 * g.nst + s0 + st];
+  }
+  __syncthreads();
+  RadixPlan<N>::template fft<T, -1, ZTHR, ZS>::run(
+      buf, ns, 1, [](int f) { return f * NPAD; }, twiddles<T>(g));
+  const double inv_n3 = 1.0 / (double(N) * N * N);
+  Tout* dst = out.base + slot * out.stride;
+  const int e0 = g.stick_off[s0], e1 = g.stick_off[s0 + ns];
+  const double eps = (mode == ZF_SHIFT) ? eps_slot[slot] : 0.0;
+  const Tout* p = (mode == ZF_SHIFT) ? pin.base + slot * pin.stride : nullptr;
+  for (int e = e0 + threadIdx.x; e < e1; e += ZTHR) {
+    const int pos = g.elem_pos[e];
+    const int st = pos / N - s0, i0 = pos - (pos / N) * N;
+    const cpx<T> v = buf[st * NPAD + i0];
+    double re = double(v.x) * inv_n3, im = double(v.y) * inv_n3;
+    if (mode == ZF_SHIFT) {
+      const double k = g.kin[e] - eps;
+      re += k * double(p[e].x);
+      im += k * double(p[e].y);
+    }
+    using TO = typename real_of<Tout>::type;
+    dst[e].x = TO(re);
+    dst[e].y = TO(im);
+  }
+}
+
+// ------------------------------------------------------------------ planes
+// LDS tile [i1][i2] with row pitch N + 1.  Rows transformed along i2 are the
+// active rows only (the others are zero before the i1 transform).
+template <int N, typename T>
+__device__ inline void plane_inverse(cpx<T>* pl, const GridDev& g, const cpx<T>* tw) {
+  constexpr int NP = N + 1;
+  const int* rows = g.row_list;
+  RadixPlan<N>::template fft<T, +1, PTHR, N>::run(
+      pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, tw);
+  RadixPlan<N>::template fft<T, +1, PTHR, N>::run(pl, N, NP, [](int f) { return f; }, tw);
+}
+
+template <int N, typename T>
+__device__ inline void plane_forward(cpx<T>* pl, const GridDev& g, const cpx<T>* tw) {
+  constexpr int NP = N + 1;
+  const int* rows = g.row_list;
+  RadixPlan<N>::template fft<T, -1, PTHR, N>::run(pl, N, NP, [](int f) { return f; }, tw);
+  RadixPlan<N>::template fft<T, -1, PTHR, N>::run(
+      pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, tw);
+}
+
+template <int N, typename T>
+__device__ inline void plane_scatter(cpx<T>* pl, const GridDev& g, const cpx<T>* row) {
+  constexpr int NP = N + 1;
+  for (int i = threadIdx.x; i < N * NP; i += PTHR) pl[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  for (int s = threadIdx.x; s < g.nst; s += PTHR) {
+    const int p = g.stick_i12[s];
+    const int i1 = p / N, i2 = p - (p / N) * N;
+    pl[i1 * NP + i2] = row[s];
+  }
+  __syncthreads();
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(PTHR) void k_plane_local(GridDev g, VecSet<cpx<T>> sticks,
+                                                       const int* slots, const T* pot,
+                                                       const T* const* pot_ptr) {
+  constexpr int NP = N + 1;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int slot = slots[blockIdx.y];
+  const int i0 = blockIdx.x;
+  cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+  const cpx<T>* tw = twiddles<T>(g);
+  plane_scatter<N, T>(pl, g, row);
+  plane_inverse<N, T>(pl, g, tw);
+  const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+  for (int e = threadIdx.x; e < N * N; e += PTHR) {
+    const int i1 = e / N, i2 = e - (e / N) * N;
+    const T v = V[e];
+    cpx<T>& c = pl[i1 * NP + i2];
+    c.x *= v;
+    c.y *= v;
+  }
+  __syncthreads();
+  plane_forward<N, T>(pl, g, tw);
+  for (int s = threadIdx.x; s < g.nst; s += PTHR) {
+    const int p = g.stick_i12[s];
+    const int i1 = p / N, i2 = p - (p / N) * N;
+    row[s] = pl[i1 * NP + i2];
+  }
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(PTHR) void k_plane_to_grid(GridDev g, VecSet<const cpx<T>> sticks,
+                                                         VecSet<cpx<T>> grid, const int* slots) {
+  constexpr int NP = N + 1;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int slot = slots[blockIdx.y];
+  const int i0 = blockIdx.x;
+  const cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+  plane_scatter<N, T>(pl, g, row);
+  plane_inverse<N, T>(pl, g, twiddles<T>(g));
+  cpx<T>* dst = grid.base + slot * grid.stride + (long long)i0 * N * N;
+  for (int e = threadIdx.x; e < N * N; e += PTHR) {
+    const int i1 = e / N, i2 = e - (e / N) * N;
+    dst[e] = pl[i1 * NP + i2];
+  }
+}
+
+// Delta n for perturbation j = blockIdx.y on plane i0 = blockIdx.x, summed over the
+// bands in a fixed order (deterministic, no atomics).
+template <int N>
+__global__ __launch_bounds__(PTHR) void k_drho(GridDev g, const z64* sticks, long long sstride,
+                                                int nband, const int* bands, const z64* psir,
+                                                double coef, double* drho) {
+  constexpr int NP = N + 1;
+  constexpr int PER = (N * N + PTHR - 1) / PTHR;
+  extern __shared__ unsigned char smem_raw[];
+  z64* pl = reinterpret_cast<z64*>(smem_raw);
+  const int j = blockIdx.y, i0 = blockIdx.x;
+  const long long n3 = (long long)N * N * N;
+  double acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+  for (int v = 0; v < nband; ++v) {
+    const z64* row = sticks + ((long long)j * nband + v) * sstride + (long long)i0 * g.nst;
+    plane_scatter<N, double>(pl, g, row);
+    plane_inverse<N, double>(pl, g, g.tw64);
+    const z64* pr = psir + (long long)bands[v] * n3 + (long long)i0 * N * N;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * PTHR;
+      if (e < N * N) {
+        const int i1 = e / N, i2 = e - (e / N) * N;
+        const z64 a = pr[e], d = pl[i1 * NP + i2];
+        acc[q] += a.x * d.x + a.y * d.y;
+      }
+    }
+    __syncthreads();
+  }
+  double* out = drho + (long long)j * n3 + (long long)i0 * N * N;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * PTHR;
+    if (e < N * N) out[e] = coef * acc[q];
+  }
+}
+
+template <int N, typename T>
+constexpr size_t plane_smem() { return size_t(N) * (N + 1) * sizeof(cpx<T>); }
+
+// Raises the dynamic LDS limit of one kernel instantiation once per process.
+template <auto K>
+void set_smem(size_t bytes) {
+  static bool done = false;
+  if (!done) {
+    STH_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(K),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done = true;
+  }
+}
+
+}  // namespace
+
+#define STH_DISPATCH_N(Nval, ...)                                                   \
+  switch (Nval) {                                                                   \
+    case 24: { constexpr int NN = 24; __VA_ARGS__; } break;                        \
+    case 48: { constexpr int NN = 48; __VA_ARGS__; } break;                        \
+    case 72: { constexpr int NN = 72; __VA_ARGS__; } break;                        \
+    case 96: { constexpr int NN = 96; __VA_ARGS__; } break;                        \
+    default: set_error("unsupported FFT grid %d (supported: 24, 48, 72, 96)", Nval); \
+             throw Error(STH_E_INVALID);                                            \
+  }
+
+template <typename T, typename Tin>
+void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
+                     const int* slots, int ncols, hipStream_t st) {
+  if (ncols <= 0) return;
+  STH_DISPATCH_N(g.N, {
+    constexpr int ZS = zsticks<NN, T>();
+    dim3 grid((g.nst + ZS - 1) / ZS, ncols);
+    hipLaunchKernelGGL((k_zfft_inv<NN, T, Tin>), grid, dim3(ZTHR), 0, st, g, in, sticks, slots);
+  });
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
+                        const T* pot, const T* const* pot_ptr, hipStream_t st) {
+  if (ncols <= 0) return;
+  dim3 grid(g.N, ncols);
+  STH_DISPATCH_N(g.N, {
+    constexpr size_t sm = plane_smem<NN, T>();
+    set_smem<k_plane_local<NN, T>>(sm);
+    hipLaunchKernelGGL((k_plane_local<NN, T>), grid, dim3(PTHR), sm, st, g, sticks, slots, pot,
+                       pot_ptr);
+  });
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T, typename Tout>
+void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout> out,
+                     const int* slots, int ncols, int mode, VecSet<const Tout> pin,
+                     const double* eps_slot, hipStream_t st) {
+  if (ncols <= 0) return;
+  STH_DISPATCH_N(g.N, {
+    constexpr int ZS = zsticks<NN, T>();
+    dim3 grid((g.nst + ZS - 1) / ZS, ncols);
+    hipLaunchKernelGGL((k_zfft_fwd<NN, T, Tout>), grid, dim3(ZTHR), 0, st, g, sticks, out, slots,
+                       mode, pin, eps_slot);
+  });
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_plane_to_grid(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<cpx<T>> grid_out,
+                          const int* slots, int ncols, hipStream_t st) {
+  if (ncols <= 0) return;
+  dim3 grid(g.N, ncols);
+  STH_DISPATCH_N(g.N, {
+    constexpr size_t sm = plane_smem<NN, T>();
+    set_smem<k_plane_to_grid<NN, T>>(sm);
+    hipLaunchKernelGGL((k_plane_to_grid<NN, T>), grid, dim3(PTHR), sm, st, g, sticks, grid_out,
+                       slots);
+  });
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, int nband,
+                 const int* bands, const z64* psir, int npert, double coef, double* drho,
+                 hipStream_t st) {
+  if (npert <= 0) return;
+  dim3 grid(g.N, npert);
+  STH_DISPATCH_N(g.N, {
+    constexpr size_t sm = plane_smem<NN, double>();
+    set_smem<k_drho<NN>>(sm);
+    hipLaunchKernelGGL((k_drho<NN>), grid, dim3(PTHR), sm, st, g, sticks, stick_stride, nband,
+                       bands, psir, coef, drho);
+  });
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template void launch_zfft_inv<double, z64>(const GridDev&, VecSet<const z64>, VecSet<z64>,
+                                           const int*, int, hipStream_t);
+template void launch_zfft_inv<float, z64>(const GridDev&, VecSet<const z64>, VecSet<z32>,
+                                          const int*, int, hipStream_t);
+template void launch_zfft_inv<float, z32>(const GridDev&, VecSet<const z32>, VecSet<z32>,
+                                          const int*, int, hipStream_t);
+template void launch_plane_local<double>(const GridDev&, VecSet<z64>, const int*, int,
+                                         const double*, const double* const*, hipStream_t);
+template void launch_plane_local<float>(const GridDev&, VecSet<z32>, const int*, int,
+                                        const float*, const float* const*, hipStream_t);
+template void launch_zfft_fwd<double, z64>(const GridDev&, VecSet<const z64>, VecSet<z64>,
+                                           const int*, int, int, VecSet<const z64>,
+                                           const double*, hipStream_t);
+template void launch_zfft_fwd<float, z64>(const GridDev&, VecSet<const z32>, VecSet<z64>,
+                                          const int*, int, int, VecSet<const z64>,
+                                          const double*, hipStream_t);
+template void launch_zfft_fwd<float, z32>(const GridDev&, VecSet<const z32>, VecSet<z32>,
+                                          const int*, int, int, VecSet<const z32>,
+                                          const double*, hipStream_t);
+template void launch_plane_to_grid<double>(const GridDev&, VecSet<const z64>, VecSet<z64>,
+                                           const int*, int, hipStream_t);
+
+}  // namespace sth

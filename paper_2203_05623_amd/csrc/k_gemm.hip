@@ -1,0 +1,246 @@
+// Dense complex contractions on the FP64 matrix cores of gfx950.
+//
+// The projector products of the Hamiltonian (V_NL = sum |beta> D <beta|) and of
+// the valence projector P_v = sum |v><v| are tall-skinny GEMMs over the sphere
+// index: C = W^H P (reduction over npw) and Y += W C (npw output rows).  They
+// run on v_mfma_f64_16x16x4f64.  A complex product is mapped onto real MFMA by
+// interleaving the reduction index: k' = 2k + t, t = 0 for the real part and 1
+// for the imaginary part; the real A' row is the interleaved storage itself and
+// the two real B' operands are (re, im) or (im, -re) picked per lane.
+//
+// MFMA f64 16x16x4 lane layout (64 lanes, l = lane):
+//   A[i][k]: i = l % 16, k = l / 16;  B[k][j]: k = l / 16, j = l % 16;
+//   D[i][j], register v: i = l / 16 + 4 v, j = l % 16   (measured on gfx950).
+#include "errors.hpp"
+#include "kernels.hpp"
+
+namespace sth {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;      // tile rows and columns
+constexpr int GK = 16;      // complex reduction elements per LDS stage
+constexpr int GTHR = 256;   // 4 waves, 2 x 2 arrangement of 32 x 32 sub-tiles
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// part[s][c][m] = sum_{k in chunk s} conj(A[m][k]) B_c[k]
+__global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const z64* __restrict__ A, int lda, int M,
+                                                    VecSet<const z64> B, const int* slots,
+                                                    int ncols, int K, int kchunk, z64* part) {
+  __shared__ z64 As[GT][GK + 1];
+  __shared__ z64 Bs[GT][GK + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT, s = blockIdx.z;
+  const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
+  d4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = d4{0, 0, 0, 0};
+  // rows of B this thread loads (fixed over the K loop)
+  const z64* brow[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int n = n0 + (tid + i * GTHR) / GK;
+    brow[i] = (n < ncols) ? B.base + (long long)slots[n] * B.stride : nullptr;
+  }
+  const int kq = lane >> 4, r16 = lane & 15;
+  for (int kb = kbeg; kb < kend; kb += GK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK, k = kb + c;
+      const int m = m0 + row;
+      As[row][c] = (m < M && k < kend) ? A[(long long)m * lda + k] : z64{0, 0};
+      Bs[row][c] = (brow[i] && k < kend) ? brow[i][k] : z64{0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK / 2; ++kk) {
+      const int c = 2 * kk + (kq >> 1);
+      const bool im = kq & 1;
+      double a[2], br[2], bi[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const z64 w = As[wm * 32 + t * 16 + r16][c];
+        a[t] = im ? w.y : w.x;
+        const z64 z = Bs[wn * 32 + t * 16 + r16][c];
+        br[t] = im ? z.y : z.x;
+        bi[t] = im ? -z.x : z.y;
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          accr[x][y] = mfma(a[x], br[y], accr[x][y]);
+          acci[x][y] = mfma(a[x], bi[y], acci[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 32 + x * 16 + kq + 4 * v;
+        const int n = n0 + wn * 32 + y * 16 + r16;
+        if (m < M && n < ncols)
+          part[((long long)s * ncols + n) * M + m] = z64{accr[x][y][v], acci[x][y][v]};
+      }
+}
+
+__global__ void k_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
+                               double sgn, z64* C) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)ncols * M) return;
+  const int m = int(i % M);
+  double re = 0.0, im = 0.0;
+  for (int s = 0; s < nsplit; ++s) {
+    const z64 v = part[(long long)s * ncols * M + i];
+    re += v.x;
+    im += v.y;
+  }
+  const double d = sgn * (diag ? diag[m] : 1.0);
+  C[i] = z64{d * re, d * im};
+}
+
+// Y_c[g] = s0 Y_c[g] + sum_m A[m][g] C[c][m]  (+ optional partial dots with dot_in)
+__global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, int lda, int M,
+                                                   const z64* __restrict__ C, VecSet<z64> Y,
+                                                   const int* slots, int ncols, int K, double s0,
+                                                   VecSet<const z64> dot_in, double* dots) {
+  __shared__ z64 Ws[GK][GT + 1];
+  __shared__ z64 Cs[GT][GK + 1];
+  __shared__ double red[2][GT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wg = wave & 1, wn = wave >> 1;
+  const int g0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  const int kq = lane >> 4, r16 = lane & 15;
+  d4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = d4{0, 0, 0, 0};
+  for (int mb = 0; mb < M; mb += GK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + i * GTHR;
+      {
+        const int mr = idx / GT, gc = idx % GT;
+        const int m = mb + mr, gg = g0 + gc;
+        Ws[mr][gc] = (m < M && gg < K) ? A[(long long)m * lda + gg] : z64{0, 0};
+      }
+      {
+        const int nr = idx / GK, mc = idx % GK;
+        const int n = n0 + nr, m = mb + mc;
+        Cs[nr][mc] = (n < ncols && m < M) ? C[(long long)n * M + m] : z64{0, 0};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK / 2; ++kk) {
+      const int mm = 2 * kk + (kq >> 1);
+      const bool im = kq & 1;
+      double a[2], br[2], bi[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const z64 w = Ws[mm][wg * 32 + t * 16 + r16];
+        a[t] = im ? w.y : w.x;
+        const z64 c = Cs[wn * 32 + t * 16 + r16][mm];
+        br[t] = im ? -c.y : c.x;
+        bi[t] = im ? c.x : c.y;
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          accr[x][y] = mfma(a[x], br[y], accr[x][y]);
+          acci[x][y] = mfma(a[x], bi[y], acci[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+  double dsum[2] = {0.0, 0.0};
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int n = n0 + wn * 32 + y * 16 + r16;
+    if (n >= ncols) continue;
+    z64* yrow = Y.base + (long long)slots[n] * Y.stride;
+    const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gg = g0 + wg * 32 + x * 16 + kq + 4 * v;
+        if (gg < K) {
+          z64 o = yrow[gg];
+          o.x = s0 * o.x + accr[x][y][v];
+          o.y = s0 * o.y + acci[x][y][v];
+          yrow[gg] = o;
+          if (drow) {
+            const z64 d = drow[gg];
+            dsum[y] += d.x * o.x + d.y * o.y;
+          }
+        }
+      }
+  }
+  if (!dots) return;
+  // sum over the 4 lane groups that share a column, then over the two g halves
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    dsum[y] += __shfl_xor(dsum[y], 16);
+    dsum[y] += __shfl_xor(dsum[y], 32);
+  }
+  if (wg == 1 && kq == 0) {
+    red[0][wn * 32 + r16] = dsum[0];
+    red[1][wn * 32 + r16] = dsum[1];
+  }
+  __syncthreads();
+  if (wg == 0 && kq == 0) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int n = n0 + wn * 32 + y * 16 + r16;
+      if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y] + red[y][wn * 32 + r16];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
+                      int ncols, int K, int kchunk, z64* part, hipStream_t st) {
+  if (ncols <= 0 || M <= 0) return;
+  const int nsplit = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
+  hipLaunchKernelGGL(k_gemm_ah_b, grid, dim3(GTHR), 0, st, A, lda, M, B, slots, ncols, K, kchunk,
+                     part);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
+                         double sgn, z64* C, hipStream_t st) {
+  const long long n = (long long)ncols * M;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
+                     nsplit, ncols, M, diag, sgn, C);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
+                     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
+                     double* dots, hipStream_t st) {
+  if (ncols <= 0) return;
+  dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
+  hipLaunchKernelGGL(k_gemm_a_c, grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols, K, s0,
+                     dot_in, dots);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace sth

@@ -1,0 +1,137 @@
+// Device-side data descriptors and kernel launchers of the Sternheimer library.
+#pragma once
+
+#include "common.hpp"
+
+namespace sth {
+
+// Geometry of the wave-function sphere on the FFT grid, all on the device.
+// Internal coefficient order is stick-major: sticks are lines along grid axis 0
+// with fixed (m1, m2), sorted by (m1, m2); inside a stick m0 runs -h..h.
+struct GridDev {
+  int N = 0;            // grid points per axis
+  int npw = 0;          // sphere size
+  int nst = 0;          // sticks
+  int nrow = 0;         // active i1 rows of a plane (rows holding at least one stick)
+  const int* stick_off = nullptr;  // [nst + 1] first sphere element of each stick
+  const int* elem_pos = nullptr;   // [npw] stick * N + i0 of each element
+  const int* stick_i12 = nullptr;  // [nst] i1 * N + i2 of each stick
+  const int* row_list = nullptr;   // [nrow] active i1 rows
+  const double* kin = nullptr;     // [npw] |G|^2 / 2
+  const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
+  const z32* tw32 = nullptr;       // [N] same, rounded to FP32
+};
+
+// A set of vectors addressed through a slot list: vector for list entry c is
+// base + slots[c] * stride.
+template <typename T>
+struct VecSet {
+  T* base;
+  long long stride;
+};
+
+enum ZfwdMode : int {
+  ZF_PLAIN = 0,   // out = FFT / N^3
+  ZF_SHIFT = 1,   // out = FFT / N^3 + (T(G) - eps_slot) * pin
+};
+
+// ---- FFT stages (T = double or float working precision) ----
+template <typename T, typename Tin>
+void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
+                     const int* slots, int ncols, hipStream_t st);
+// Potential of list entry c: pot_ptr[slots[c]] if pot_ptr is given, else pot.
+template <typename T>
+void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
+                        const T* pot, const T* const* pot_ptr, hipStream_t st);
+template <typename T, typename Tout>
+void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout> out,
+                     const int* slots, int ncols, int mode, VecSet<const Tout> pin,
+                     const double* eps_slot, hipStream_t st);
+template <typename T>
+void launch_plane_to_grid(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<cpx<T>> grid,
+                          const int* slots, int ncols, hipStream_t st);
+// Delta n_j(r) = coef * sum_v Re[conj(psi_v(r)) dpsi_jv(r)]; the sticks of dpsi_jv
+// are at sticks.base + (j * nband + v) * sticks.stride, psi_v(r) at psir + band[v] * N^3.
+void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, int nband,
+                 const int* bands, const z64* psir, int npert, double coef, double* drho,
+                 hipStream_t st);
+
+// ---- dense contractions on MFMA (FP64) ----
+// part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)
+void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
+                      int ncols, int K, int kchunk, z64* part, hipStream_t st);
+// C[c][m] = diag[m] * sum_s part[s][c][m]   (diag may be null -> 1)
+void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
+                         double sgn, z64* C, hipStream_t st);
+// Y_c[g] = s0 * Y_c[g] + sum_m A[m][g] C[c][m]; if dot_in, also
+// dots[c][tile] = sum_{g in tile} Re(conj(dot_in_c[g]) Y_c[g]) for 64-wide tiles of g.
+void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
+                     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
+                     double* dots, hipStream_t st);
+inline int gemm_a_c_tiles(int K) { return (K + 63) / 64; }
+
+// ---- CG vector kernels (FP64) ----
+struct SlotState {
+  double* rho;       // [nslots] <r, K r>
+  double* bnorm2;    // [nslots] ||b||^2
+  double* rnorm2;    // [nslots] ||r||^2 (last)
+  double* alpha;     // [nslots]
+  double* beta;      // [nslots]
+  double* eps;       // [nslots] eps_v of the slot's band
+  double* ekin;      // [nslots] kinetic energy of the slot's band (preconditioner)
+  double* tol;       // [nslots] relative residual target of the slot's solve
+  int* status;       // [nslots] SLOT_*
+  int* iters;        // [nslots]
+  int* maxit;        // [nslots]
+};
+enum SlotStatus : int {
+  SLOT_FREE = 0,
+  SLOT_ACTIVE = 1,
+  SLOT_CHECK = 2,       // recursive residual below tol: true residual pending
+  SLOT_DONE = 3,
+  SLOT_MAXIT = 4,
+  SLOT_BREAKDOWN = 5,
+  SLOT_NAN = 6,
+};
+inline int cg_chunks(int npw) { return (npw + 1023) / 1024; }
+
+// r = b, x = 0, p = K b; partials of <b, K b> and ||b||^2
+void launch_cg_init(const GridDev& g, VecSet<const z64> b, VecSet<z64> x, VecSet<z64> r,
+                    VecSet<z64> p, const int* slots, int ncols, const double* ekin,
+                    double* part2, hipStream_t st);
+// rho = sum part[0], bnorm2 = sum part[1]; status ACTIVE (or DONE if b == 0)
+void launch_cg_init_scalars(const double* part2, int nchunk, const int* slots, int ncols,
+                            SlotState s, hipStream_t st);
+// alpha = rho / sum(dots); breakdown when <p, A p> <= 0
+void launch_cg_alpha(const double* dots, int ntile, const int* slots, int ncols, SlotState s,
+                     hipStream_t st);
+// x += alpha p; r -= alpha q; partials of <r, K r>, ||r||^2
+void launch_cg_update_xr(const GridDev& g, VecSet<z64> x, VecSet<z64> r, VecSet<const z64> p,
+                         VecSet<const z64> q, const int* slots, int ncols, SlotState s,
+                         double* part2, hipStream_t st);
+// beta, rho, convergence test ||r||^2 <= tol^2 ||b||^2, iteration count, maxit
+void launch_cg_beta(const double* part2, int nchunk, const int* slots, int ncols, SlotState s,
+                    hipStream_t st);
+// p = K r + beta p
+void launch_cg_update_p(const GridDev& g, VecSet<const z64> r, VecSet<z64> p, const int* slots,
+                        int ncols, SlotState s, hipStream_t st);
+// r = b - q (true residual) and partial ||r||^2 (part2 layout as above; <r,Kr> too)
+void launch_cg_true_resid(const GridDev& g, VecSet<const z64> b, VecSet<const z64> q,
+                          VecSet<z64> r, const int* slots, int ncols, const double* ekin_slot,
+                          double* part2, hipStream_t st);
+// after a true residual: DONE if ||r|| <= tol ||b||, else restart (rho = <r, K r>, beta = 0)
+void launch_cg_check_true(const double* part2, int nchunk, const int* slots, int ncols,
+                          SlotState s, hipStream_t st);
+
+// ---- small helpers ----
+void launch_copy_vecs(VecSet<const z64> src, VecSet<z64> dst, const int* slots_src,
+                      const int* slots_dst, int ncols, int n, hipStream_t st);
+void launch_scale_vecs(VecSet<z64> v, const int* slots, int ncols, int n, double s,
+                       hipStream_t st);
+void launch_permute_in(const z64* src, long long sstride, z64* dst, long long dstride,
+                       const int* perm, int n, int ncols, hipStream_t st);
+void launch_permute_out(const z64* src, long long sstride, z64* dst, long long dstride,
+                        const int* perm, int n, int ncols, hipStream_t st);
+void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
+
+}  // namespace sth

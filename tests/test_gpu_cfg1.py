@@ -1,0 +1,88 @@
+"""GPU parity of the HIP path against the oracle on the tiny crystal (config 1).
+
+Calls go through the C-ABI (ctypes binding).  Tolerances: FP64 throughout;
+H.psi to 1e-12 relative (two FFT routes in FP64), Delta psi / Delta n / chi0 to
+1e-10 relative at solve tolerance 1e-12 (the workload's FP64 parity bound).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+NV = 8
+
+
+@pytest.fixture(scope="module")
+def sth():
+    import paper_2203_05623_amd as P
+    ctx = P.sth_create(device=0, max_slots=256)
+    yield P, ctx
+    P.sth_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def cfg1(cfg1_system, cfg1_dense):
+    H, w, V = cfg1_dense
+    cfg = workloads.get_config("cfg1")
+    return cfg, cfg1_system, H, w[:NV], np.ascontiguousarray(V[:NV])
+
+
+@pytest.fixture(scope="module")
+def sys1(sth, cfg1):
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, Psi, eps)
+    return sid
+
+
+def test_apply_h_matches_oracle(sth, cfg1, sys1):
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    rng = np.random.default_rng(11)
+    c = rng.standard_normal((37, s.npw)) + 1j * rng.standard_normal((37, s.npw))
+    got = P.sth_apply_h(ctx, sys1, c)
+    ref = oracle.apply_H(s, c)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("apply_h rel err", err)
+    assert err < 1e-12
+
+
+def test_solves_match_oracle(sth, cfg1, sys1):
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    npert = cfg.npert
+    dv = workloads.dv_block(cfg, range(npert))
+    bands = np.arange(NV)
+    t = P.sth_submit_solves(ctx, sys1, dv, bands, tol=1e-12, want_dpsi=True)
+    assert P.sth_wait(ctx, t, 120.0)
+    info = P.sth_poll(ctx, t)
+    assert info["n_converged"] == npert * NV
+    dpsi = np.empty((npert, NV, s.npw), np.complex128)
+    P.sth_fetch_dpsi(ctx, t, dpsi)
+    drho = np.empty((npert, cfg.N, cfg.N, cfg.N))
+    P.sth_fetch_drho(ctx, t, drho)
+    iters, resid, status, lat = P.sth_fetch_stats(ctx, t, npert * NV)
+    assert np.all(status == 0) and np.all(resid <= 1e-12)
+    print("iters min/mean/max", iters.min(), iters.mean(), iters.max())
+    # oracle: dense LU solve of the projected equation for every (j, v)
+    X = np.empty_like(dpsi)
+    for v in range(NV):
+        B = np.stack([oracle.rhs(s, Psi, v, dv[j]) for j in range(npert)], 1)
+        X[:, v] = oracle.solve_lu(H, Psi, eps[v], B).T
+    rel = np.linalg.norm(dpsi - X, axis=2) / np.linalg.norm(X, axis=2)
+    print("dpsi max rel err", rel.max())
+    assert rel.max() < 1e-10
+    dn_ref = np.stack([oracle.drho(s, Psi, X[j]) for j in range(npert)])
+    err = np.abs(drho - dn_ref).max() / np.abs(dn_ref).max()
+    print("drho rel err", err)
+    assert err < 1e-10
+    M, S, lam = P.sth_chi0_block(ctx, t, npert)
+    lam_ref, M_ref, S_ref = oracle.chi0_block(s, dv, dn_ref)
+    print("chi0 lam", lam[:4], lam_ref[:4])
+    assert np.abs(M - M_ref).max() < 1e-10 * np.abs(M_ref).max()
+    assert np.abs(S - S_ref).max() < 1e-12
+    assert np.abs(lam - lam_ref).max() < 1e-10 * np.abs(lam_ref).max()
+    P.sth_release_ticket(ctx, t)
