@@ -115,6 +115,7 @@ typedef struct {
   double t_submit, t_start, t_done;   /* seconds on the library's monotonic clock */
   long long cg_iterations;  /* sum of CG iterations over finished solves */
   long long op_applications;/* operator applications incl. true-residual checks */
+  long long op_applications_fp32; /* of which with the FP32 inner operator (STH_MIXED) */
 } sth_ticket_info;
 
 /* Creates a context on cfg->device (cfg may be NULL for defaults).  Starts the
@@ -189,6 +190,20 @@ sth_status sth_chi0_block(sth_ctx* ctx, uint64_t ticket, double* M, double* S, d
 
 /* Frees a finished ticket's device results. */
 sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket);
+
+/* Kernel timing of the solve server, for measurement: with enable != 0 the
+ * library records HIP events (on its own stream) around every kernel launch
+ * of the CG iterations, grouped by phase:
+ *   0 z-stick inverse FFT, 1 plane FFT pass, 2 z-stick forward FFT,
+ *   3 projection GEMM C = W^H P, 4 partial-sum reduction, 5 GEMM Y += W C,
+ *   6 CG vector kernels, 7 right-hand side and retirement work.
+ * sth_profile_read returns, per phase, the summed kernel time (ms), the launch
+ * count, and the algorithmic HBM bytes and flops of those launches (the
+ * method's minimum traffic / arithmetic, not hardware counters).  Reading
+ * resets the counters. */
+sth_status sth_profile(sth_ctx* ctx, int enable);
+sth_status sth_profile_read(sth_ctx* ctx, double* ms /*[8]*/, long long* launches /*[8]*/,
+                            double* bytes /*[8]*/, double* flops /*[8]*/);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* sth_last_error(void);

@@ -25,7 +25,8 @@ SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
            "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
            "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
-           "sth_last_error"]
+           "sth_profile", "sth_profile_read", "sth_last_error"]
+PHASES = ["zfft_inv", "plane", "zfft_fwd", "gemm_ah_b", "reduce", "gemm_a_c", "cg", "rhs_retire"]
 
 
 class sth_config(C.Structure):
@@ -49,7 +50,8 @@ class sth_ticket_info(C.Structure):
     _fields_ = [("state", C.c_int), ("n_total", C.c_int), ("n_finished", C.c_int),
                 ("n_converged", C.c_int), ("max_rel_resid", C.c_double),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("cg_iterations", C.c_longlong), ("op_applications", C.c_longlong)]
+                ("cg_iterations", C.c_longlong), ("op_applications", C.c_longlong),
+                ("op_applications_fp32", C.c_longlong)]
 
 
 class SthError(RuntimeError):
@@ -80,6 +82,8 @@ def load():
         "sth_fetch_stats": [vp, u64, vp, vp, vp, vp],
         "sth_chi0_block": [vp, u64, vp, vp, vp],
         "sth_release_ticket": [vp, u64],
+        "sth_profile": [vp, C.c_int],
+        "sth_profile_read": [vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -282,6 +286,21 @@ def sth_chi0_block(ctx, ticket, npert):
 
 def sth_release_ticket(ctx, ticket):
     _check(lib().sth_release_ticket(ctx, ticket))
+
+
+def sth_profile(ctx, enable=True):
+    _check(lib().sth_profile(ctx, int(bool(enable))))
+
+
+def sth_profile_read(ctx):
+    """{phase: (ms, launches, algorithmic bytes, flops)}; resets the counters."""
+    ms = np.zeros(8)
+    n = np.zeros(8, np.int64)
+    b = np.zeros(8)
+    f = np.zeros(8)
+    _check(lib().sth_profile_read(ctx, ms.ctypes.data, n.ctypes.data, b.ctypes.data,
+                                  f.ctypes.data))
+    return {PHASES[i]: (float(ms[i]), int(n[i]), float(b[i]), float(f[i])) for i in range(8)}
 
 
 def sth_last_error():

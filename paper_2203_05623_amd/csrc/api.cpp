@@ -170,6 +170,15 @@ sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket) {
   return guard([&] { ctx_of(ctx)->release_ticket(ticket); });
 }
 
+sth_status sth_profile(sth_ctx* ctx, int enable) {
+  return guard([&] { ctx_of(ctx)->profile(enable != 0); });
+}
+
+sth_status sth_profile_read(sth_ctx* ctx, double* ms, long long* launches, double* bytes,
+                            double* flops) {
+  return guard([&] { ctx_of(ctx)->profile_read(ms, launches, bytes, flops); });
+}
+
 const char* sth_last_error(void) { return sth::g_err; }
 
 }  // extern "C"

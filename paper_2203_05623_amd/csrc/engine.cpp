@@ -156,6 +156,11 @@ Context::~Context() {
   (void)hipStreamSynchronize(st_);
   tickets_.clear();
   systems_.clear();
+  for (auto& r : prof_recs_) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
   (void)hipStreamDestroy(st_);
 }
 
@@ -196,12 +201,6 @@ std::shared_ptr<Request> Context::find(uint64_t t) {
 
 // ------------------------------------------------------------------ system setup
 namespace {
-
-struct StickBuild {
-  std::vector<int> perm;        // caller -> internal
-  std::vector<int> stick_off, elem_pos, stick_i12, row_list;
-  std::vector<double> kin;
-};
 
 StickBuild build_sticks(const int32_t* mil, int npw, int N, double L) {
   StickBuild s;
@@ -264,30 +263,28 @@ void Context::alloc_slots(System& s, int nslots) {
   s.d_q = DevMem(&budget_, vec);
   s.d_b = DevMem(&budget_, vec);
   s.d_sticks = DevMem(&budget_, (size_t)nslots * N * s.nst * sizeof(z64));
-  s.kchunk = 2048;
-  s.nsplit = (s.npw + s.kchunk - 1) / s.kchunk;
-  s.ntile = gemm_a_c_tiles(s.npw);
-  s.nchunk = cg_chunks(s.npw);
   const int mrows = std::max(s.M, 1);
   s.d_part = DevMem(&budget_, (size_t)s.nsplit * nslots * mrows * sizeof(z64));
   s.d_C = DevMem(&budget_, (size_t)nslots * mrows * sizeof(z64));
   s.d_dots = DevMem(&budget_, (size_t)nslots * s.ntile * sizeof(double));
   s.d_part2 = DevMem(&budget_, (size_t)nslots * s.nchunk * 2 * sizeof(double));
-  s.d_ss_d = DevMem(&budget_, (size_t)8 * nslots * sizeof(double));
-  s.d_ss_i = DevMem(&budget_, (size_t)3 * nslots * sizeof(int));
+  s.d_ss_d = DevMem(&budget_, (size_t)9 * nslots * sizeof(double));
+  s.d_ss_i = DevMem(&budget_, (size_t)4 * nslots * sizeof(int));
   s.d_ss_d.zero(st_);
   s.d_ss_i.zero(st_);
   double* dd = s.d_ss_d.as<double>();
   int* di = s.d_ss_i.as<int>();
+  // rho, bnorm2, rnorm2, alpha, beta, eps, ekin, tol, tgt2 | status, iters, maxit, prec
   s.ss = SlotState{dd, dd + nslots, dd + 2 * nslots, dd + 3 * nslots, dd + 4 * nslots,
-                   dd + 5 * nslots, dd + 6 * nslots, dd + 7 * nslots, di, di + nslots,
-                   di + 2 * nslots};
+                   dd + 5 * nslots, dd + 6 * nslots, dd + 7 * nslots, dd + 8 * nslots,
+                   di, di + nslots, di + 2 * nslots, di + 3 * nslots};
   s.d_potptr = DevMem(&budget_, (size_t)nslots * sizeof(double*));
   const int arena = 16 * nslots + 4 * std::max(s.nv, 1) + 4096;
   s.d_lists = DevMem(&budget_, (size_t)arena * sizeof(int));
   s.h_lists = HostMem((size_t)arena * sizeof(int));
   s.h_potptr = HostMem((size_t)nslots * sizeof(double*));
-  s.h_eps = HostMem((size_t)nslots * sizeof(double) * 4);   // eps, ekin, tol, maxit (as int)
+  // host mirrors of the per-slot constants: eps, ekin, tol (double), maxit, prec (int)
+  s.h_eps = HostMem((size_t)nslots * sizeof(double) * 5);
   s.h_status = HostMem((size_t)nslots * sizeof(int) * 2);
   s.h_rn2 = HostMem((size_t)nslots * sizeof(double) * 2);
   s.slots.assign(nslots, SlotHost{});
@@ -307,28 +304,13 @@ int* Context::upload_list(System& s, const std::vector<int>& v) {
   return d;
 }
 
-int Context::set_system(const sth_system_desc& d, hipStream_t user) {
-  check_ptr_kind(d.ptr_kind);
-  if (!(d.L > 0) || d.npw <= 0 || !d.miller || !d.vloc_r || d.nv < 1 || !d.psi_v || !d.eps_v ||
-      d.nproj < 0 || (d.nproj > 0 && (!d.beta || !d.dij)) || d.nv >= d.npw) {
-    set_error("invalid system description (L, npw, miller, vloc_r, nv>=1, psi_v, eps_v, "
-              "beta/dij when nproj>0, nv < npw)");
-    throw Error(STH_E_INVALID);
-  }
-  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96) {
-    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96)", d.n);
-    throw Error(STH_E_INVALID);
-  }
-  std::lock_guard<std::mutex> glk(gpu_mu_);
-  STH_HIP_CHECK(hipSetDevice(device_));
-  order_after(user);
-  auto sp = std::make_unique<System>();
-  System& s = *sp;
+// Geometry, potentials and W = [psi_v (nv rows, may be 0); beta] of a system on the device.
+StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) {
   s.N = d.n;
   s.npw = d.npw;
-  s.nv = d.nv;
+  s.nv = nv;
   s.nproj = d.nproj;
-  s.M = d.nv + d.nproj;
+  s.M = nv + d.nproj;
   s.L = d.L;
   s.omega = d.L * d.L * d.L;
   s.fs = d.spin_factor;
@@ -338,20 +320,6 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   s.perm = sb.perm;
   const int N = s.N;
   const long long n3 = (long long)N * N * N;
-
-  // host copies of the small per-band inputs
-  std::vector<double> eps(d.nv);
-  if (d.ptr_kind == STH_PTR_DEVICE)
-    STH_HIP_CHECK(hipMemcpy(eps.data(), d.eps_v, d.nv * sizeof(double), hipMemcpyDeviceToHost));
-  else
-    std::memcpy(eps.data(), d.eps_v, d.nv * sizeof(double));
-  for (int v = 1; v < d.nv; ++v)
-    if (!(eps[v] >= eps[v - 1])) {
-      set_error("eps_v must be ascending (band %d)", v);
-      throw Error(STH_E_INVALID);
-    }
-  s.eps = eps;
-  s.alpha_pv = std::max(2.0 * (eps.back() - eps.front()), 1.0);
 
   s.d_stick_off = upload(&budget_, sb.stick_off, st_);
   s.d_elem_pos = upload(&budget_, sb.elem_pos, st_);
@@ -379,14 +347,20 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   s.g.kin = s.d_kin.as<double>();
   s.g.tw64 = s.d_tw64.as<z64>();
   s.g.tw32 = s.d_tw32.as<z32>();
+  s.kchunk = 2048;
+  s.nsplit = (s.npw + s.kchunk - 1) / s.kchunk;
+  s.ntile = gemm_a_c_tiles(s.npw);
+  s.nchunk = cg_chunks(s.npw);
 
   // W = [psi_v; beta] in internal order, diag = [alpha_pv; D]
   s.d_W = DevMem(&budget_, (size_t)s.M * s.npw * sizeof(z64));
   {
-    DevMem tmp(&budget_, (size_t)std::max(s.nv, s.nproj) * s.npw * sizeof(z64));
-    copy_in(tmp.as<void>(), d.psi_v, (size_t)s.nv * s.npw * sizeof(z64), d.ptr_kind, st_);
-    launch_permute_in(tmp.as<z64>(), s.npw, s.d_W.as<z64>(), s.npw, s.d_perm.as<int>(), s.npw,
-                      s.nv, st_);
+    DevMem tmp(&budget_, (size_t)std::max({s.nv, s.nproj, 1}) * s.npw * sizeof(z64));
+    if (s.nv) {
+      copy_in(tmp.as<void>(), d.psi_v, (size_t)s.nv * s.npw * sizeof(z64), d.ptr_kind, st_);
+      launch_permute_in(tmp.as<z64>(), s.npw, s.d_W.as<z64>(), s.npw, s.d_perm.as<int>(), s.npw,
+                        s.nv, st_);
+    }
     if (s.nproj) {
       copy_in(tmp.as<void>(), d.beta, (size_t)s.nproj * s.npw * sizeof(z64), d.ptr_kind, st_);
       launch_permute_in(tmp.as<z64>(), s.npw, s.d_W.as<z64>() + (size_t)s.nv * s.npw, s.npw,
@@ -407,6 +381,48 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   s.d_diag = upload(&budget_, diag, st_);
   s.d_vloc = DevMem(&budget_, n3 * sizeof(double));
   copy_in(s.d_vloc.as<void>(), d.vloc_r, n3 * sizeof(double), d.ptr_kind, st_);
+  // FP32 copies for the inner operator of mixed-precision solves (rounded once)
+  s.d_W32 = DevMem(&budget_, (size_t)s.M * s.npw * sizeof(z32));
+  launch_z64_to_z32(s.d_W.as<z64>(), s.d_W32.as<z32>(), (long long)s.M * s.npw, st_);
+  s.d_vloc32 = DevMem(&budget_, n3 * sizeof(float));
+  launch_to_f32(s.d_vloc.as<double>(), s.d_vloc32.as<float>(), n3, st_);
+  STH_HIP_CHECK(hipStreamSynchronize(st_));
+  return sb;
+}
+
+int Context::set_system(const sth_system_desc& d, hipStream_t user) {
+  check_ptr_kind(d.ptr_kind);
+  if (!(d.L > 0) || d.npw <= 0 || !d.miller || !d.vloc_r || d.nv < 1 || !d.psi_v || !d.eps_v ||
+      d.nproj < 0 || (d.nproj > 0 && (!d.beta || !d.dij)) || d.nv >= d.npw) {
+    set_error("invalid system description (L, npw, miller, vloc_r, nv>=1, psi_v, eps_v, "
+              "beta/dij when nproj>0, nv < npw)");
+    throw Error(STH_E_INVALID);
+  }
+  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96) {
+    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96)", d.n);
+    throw Error(STH_E_INVALID);
+  }
+  std::lock_guard<std::mutex> glk(gpu_mu_);
+  STH_HIP_CHECK(hipSetDevice(device_));
+  order_after(user);
+  auto sp = std::make_unique<System>();
+  System& s = *sp;
+  // host copies of the small per-band inputs
+  std::vector<double> eps(d.nv);
+  if (d.ptr_kind == STH_PTR_DEVICE)
+    STH_HIP_CHECK(hipMemcpy(eps.data(), d.eps_v, d.nv * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(eps.data(), d.eps_v, d.nv * sizeof(double));
+  for (int v = 1; v < d.nv; ++v)
+    if (!(eps[v] >= eps[v - 1])) {
+      set_error("eps_v must be ascending (band %d)", v);
+      throw Error(STH_E_INVALID);
+    }
+  s.eps = eps;
+  s.alpha_pv = std::max(2.0 * (eps.back() - eps.front()), 1.0);
+  StickBuild sb = setup_geometry(s, d, d.nv);
+  const int N = s.N;
+  const long long n3 = (long long)N * N * N;
   s.d_eps_band = upload(&budget_, eps, st_);
 
   // slot pool
@@ -516,19 +532,175 @@ void Context::release_system(int id) {
 // out = (H - eps_slot) in + W diag W^H in, on the listed vectors (slot pool
 // scratch: sticks, part, C).  With `dots`, partial Re<in, out> per 64-row tile.
 void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                       bool dots) {
+                       bool dots, bool fp32) {
+  if (fp32) {
+    apply_op32(s, in, out, dl, n, dots);
+    return;
+  }
   const int N = s.N;
+  const double z = sizeof(z64), vb = double(s.npw) * z, sb = double(N) * s.nst * z;
+  const double gf = 8.0 * s.M * double(s.npw) * n;
   VecSet<z64> sticks{s.d_sticks.as<z64>(), (long long)N * s.nst};
+  int h = prof_begin(PH_ZINV);
   launch_zfft_inv<double, z64>(s.g, in, sticks, dl, n, st_);
+  prof_end(h, n * (vb + sb), 0.0);
+  h = prof_begin(PH_PLANE);
   launch_plane_local<double>(s.g, sticks, dl, n, s.d_vloc.as<double>(), nullptr, st_);
+  prof_end(h, n * 2.0 * sb + double(N) * N * N * 8.0, 0.0);
+  h = prof_begin(PH_ZFWD);
   launch_zfft_fwd<double, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
                                s.ss.eps, st_);
+  prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   // the GEMM partials are indexed by list position; the slot list maps them back
+  h = prof_begin(PH_GEMM_AHB);
   launch_gemm_ah_b(s.W(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, s.d_part.as<z64>(), st_);
+  prof_end(h, s.M * vb + n * vb, gf);
+  h = prof_begin(PH_REDUCE);
   launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.M, s.d_diag.as<double>(), 1.0,
                       s.d_C.as<z64>(), st_);
+  prof_end(h, (s.nsplit + 1.0) * n * s.M * z, 0.0);
+  h = prof_begin(PH_GEMM_AC);
   launch_gemm_a_c(s.W(), s.npw, s.M, s.d_C.as<z64>(), out, dl, n, s.npw, 1.0, in,
                   dots ? s.d_dots.as<double>() : nullptr, st_);
+  prof_end(h, s.M * vb + n * vb * (dots ? 3.0 : 2.0), gf);
+}
+
+// The same operator with the FFT passes, V_loc and the projector GEMMs in FP32
+// (inner iterations of mixed-precision solves); the kinetic and shift terms
+// and every vector in memory stay FP64.
+void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
+                         bool dots) {
+  const int N = s.N;
+  const double vb = double(s.npw) * sizeof(z64), sb = double(N) * s.nst * sizeof(z32);
+  const double gf = 8.0 * s.M * double(s.npw) * n;
+  VecSet<z32> sticks{reinterpret_cast<z32*>(s.d_sticks.as<z64>()), (long long)N * s.nst};
+  z32* part = reinterpret_cast<z32*>(s.d_part.as<z64>());
+  z32* C = reinterpret_cast<z32*>(s.d_C.as<z64>());
+  int h = prof_begin(PH_ZINV);
+  launch_zfft_inv<float, z64>(s.g, in, sticks, dl, n, st_);
+  prof_end(h, n * (vb + sb), 0.0);
+  h = prof_begin(PH_PLANE);
+  launch_plane_local<float>(s.g, sticks, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
+  prof_end(h, n * 2.0 * sb + double(N) * N * N * 4.0, 0.0);
+  h = prof_begin(PH_ZFWD);
+  launch_zfft_fwd<float, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
+                              s.ss.eps, st_);
+  prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
+  h = prof_begin(PH_GEMM_AHB);
+  launch_gemm_ah_b(s.d_W32.as<z32>(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, part, st_);
+  prof_end(h, s.M * vb / 2 + n * vb, gf);
+  h = prof_begin(PH_REDUCE);
+  launch_reduce_parts(part, s.nsplit, n, s.M, s.d_diag.as<double>(), 1.0, C, st_);
+  prof_end(h, (s.nsplit + 1.0) * n * s.M * sizeof(z32), 0.0);
+  h = prof_begin(PH_GEMM_AC);
+  launch_gemm_a_c(s.d_W32.as<z32>(), s.npw, s.M, C, out, dl, n, s.npw, 1.0, in,
+                  dots ? s.d_dots.as<double>() : nullptr, st_);
+  prof_end(h, s.M * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
+}
+
+// ------------------------------------------------------------------ profiling
+void Context::profile(bool on) {
+  std::lock_guard<std::mutex> glk(gpu_mu_);
+  STH_HIP_CHECK(hipStreamSynchronize(st_));
+  prof_harvest();
+  prof_on_ = on;
+}
+
+int Context::prof_begin(int phase) {
+  if (!prof_on_) return -1;
+  std::lock_guard<std::mutex> lk(prof_mu_);
+  ProfRec r{phase, nullptr, nullptr, 0.0, 0.0};
+  for (hipEvent_t* e : {&r.a, &r.b}) {
+    if (!ev_pool_.empty()) {
+      *e = ev_pool_.back();
+      ev_pool_.pop_back();
+    } else {
+      STH_HIP_CHECK(hipEventCreate(e));
+    }
+  }
+  STH_HIP_CHECK(hipEventRecord(r.a, st_));
+  prof_recs_.push_back(r);
+  return int(prof_recs_.size()) - 1;
+}
+
+void Context::prof_end(int handle, double bytes, double flops) {
+  if (handle < 0) return;
+  std::lock_guard<std::mutex> lk(prof_mu_);
+  ProfRec& r = prof_recs_[handle];
+  r.bytes = bytes;
+  r.flops = flops;
+  STH_HIP_CHECK(hipEventRecord(r.b, st_));
+}
+
+void Context::prof_harvest() {
+  std::lock_guard<std::mutex> lk(prof_mu_);
+  for (ProfRec& r : prof_recs_) {
+    float ms = 0.0f;
+    STH_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    prof_ms_[r.phase] += ms;
+    prof_bytes_[r.phase] += r.bytes;
+    prof_flops_[r.phase] += r.flops;
+    prof_n_[r.phase] += 1;
+    ev_pool_.push_back(r.a);
+    ev_pool_.push_back(r.b);
+  }
+  prof_recs_.clear();
+}
+
+void Context::profile_read(double* ms, long long* n, double* bytes, double* flops) {
+  std::lock_guard<std::mutex> glk(gpu_mu_);
+  STH_HIP_CHECK(hipStreamSynchronize(st_));
+  prof_harvest();
+  std::lock_guard<std::mutex> lk(prof_mu_);
+  for (int p = 0; p < NPH; ++p) {
+    if (ms) ms[p] = prof_ms_[p];
+    if (n) n[p] = prof_n_[p];
+    if (bytes) bytes[p] = prof_bytes_[p];
+    if (flops) flops[p] = prof_flops_[p];
+    prof_ms_[p] = prof_bytes_[p] = prof_flops_[p] = 0.0;
+    prof_n_[p] = 0;
+  }
+}
+
+void Context::h_scratch(System& s, HScratch& w, int cap) {
+  const int mp = std::max(s.nproj, 1);
+  w.cap = cap;
+  w.sticks = DevMem(&budget_, (size_t)cap * s.N * s.nst * sizeof(z64));
+  w.part = DevMem(&budget_, (size_t)s.nsplit * cap * mp * sizeof(z64));
+  w.C = DevMem(&budget_, (size_t)cap * mp * sizeof(z64));
+  w.zeros = DevMem(&budget_, (size_t)cap * sizeof(double));
+  w.ids = DevMem(&budget_, (size_t)cap * sizeof(int));
+  w.zeros.zero(st_);
+  std::vector<int> idv(cap);
+  std::iota(idv.begin(), idv.end(), 0);
+  STH_HIP_CHECK(hipMemcpyAsync(w.ids.as<void>(), idv.data(), cap * sizeof(int),
+                               hipMemcpyHostToDevice, st_));
+  STH_HIP_CHECK(hipStreamSynchronize(st_));
+}
+
+// out = H in for n contiguous vectors (internal order): T + V_loc by the
+// dual-space FFT route, V_NL by the projector GEMMs.
+void Context::h_block(System& s, HScratch& w, const z64* in, z64* out, int n) {
+  const int N = s.N;
+  for (int c0 = 0; c0 < n; c0 += w.cap) {
+    const int nc = std::min(w.cap, n - c0);
+    VecSet<const z64> vin{in + (size_t)c0 * s.npw, (long long)s.npw};
+    VecSet<z64> vout{out + (size_t)c0 * s.npw, (long long)s.npw};
+    VecSet<z64> st{w.sticks.as<z64>(), (long long)N * s.nst};
+    const int* ids = w.ids.as<int>();
+    launch_zfft_inv<double, z64>(s.g, vin, st, ids, nc, st_);
+    launch_plane_local<double>(s.g, st, ids, nc, s.d_vloc.as<double>(), nullptr, st_);
+    launch_zfft_fwd<double, z64>(s.g, {st.base, st.stride}, vout, ids, nc, ZF_SHIFT, vin,
+                                 w.zeros.as<double>(), st_);
+    if (s.nproj) {
+      launch_gemm_ah_b(s.beta(), s.npw, s.nproj, vin, ids, nc, s.npw, s.kchunk,
+                       w.part.as<z64>(), st_);
+      launch_reduce_parts(w.part.as<z64>(), s.nsplit, nc, s.nproj, s.d_diag.as<double>() + s.nv,
+                          1.0, w.C.as<z64>(), st_);
+      launch_gemm_a_c(s.beta(), s.npw, s.nproj, w.C.as<z64>(), vout, ids, nc, s.npw, 1.0,
+                      {nullptr, 0}, nullptr, st_);
+    }
+  }
 }
 
 void Context::apply_h(int id, int nvec, const double* in, double* out, int ptr_kind,
@@ -543,41 +715,18 @@ void Context::apply_h(int id, int nvec, const double* in, double* out, int ptr_k
   System& s = sys(id);
   if (nvec == 0) return;
   order_after(user);
-  const int N = s.N;
   const int chunk = std::min(nvec, 256);
   const size_t vb = (size_t)s.npw * sizeof(z64);
   DevMem tin(&budget_, (size_t)chunk * vb), tout(&budget_, (size_t)chunk * vb);
   DevMem a(&budget_, (size_t)chunk * vb), bq(&budget_, (size_t)chunk * vb);
-  DevMem sticks(&budget_, (size_t)chunk * N * s.nst * sizeof(z64));
-  const int nsplit = s.nsplit;
-  DevMem part(&budget_, (size_t)nsplit * chunk * std::max(s.nproj, 1) * sizeof(z64));
-  DevMem C(&budget_, (size_t)chunk * std::max(s.nproj, 1) * sizeof(z64));
-  DevMem zeros(&budget_, (size_t)chunk * sizeof(double));
-  DevMem ids(&budget_, (size_t)chunk * sizeof(int));
-  zeros.zero(st_);
-  std::vector<int> idv(chunk);
-  std::iota(idv.begin(), idv.end(), 0);
-  STH_HIP_CHECK(hipMemcpyAsync(ids.as<void>(), idv.data(), chunk * sizeof(int),
-                               hipMemcpyHostToDevice, st_));
+  HScratch w;
+  h_scratch(s, w, chunk);
   for (int c0 = 0; c0 < nvec; c0 += chunk) {
     const int nc = std::min(chunk, nvec - c0);
     copy_in(tin.as<void>(), in + (size_t)c0 * s.npw * 2, (size_t)nc * vb, ptr_kind, st_);
     launch_permute_in(tin.as<z64>(), s.npw, a.as<z64>(), s.npw, s.d_perm.as<int>(), s.npw, nc,
                       st_);
-    VecSet<z64> st{sticks.as<z64>(), (long long)N * s.nst};
-    launch_zfft_inv<double, z64>(s.g, {a.as<const z64>(), s.npw}, st, ids.as<int>(), nc, st_);
-    launch_plane_local<double>(s.g, st, ids.as<int>(), nc, s.d_vloc.as<double>(), nullptr, st_);
-    launch_zfft_fwd<double, z64>(s.g, {st.base, st.stride}, {bq.as<z64>(), s.npw}, ids.as<int>(),
-                                 nc, ZF_SHIFT, {a.as<const z64>(), s.npw}, zeros.as<double>(),
-                                 st_);
-    if (s.nproj) {
-      launch_gemm_ah_b(s.beta(), s.npw, s.nproj, {a.as<const z64>(), s.npw}, ids.as<int>(), nc,
-                       s.npw, s.kchunk, part.as<z64>(), st_);
-      launch_reduce_parts(part.as<z64>(), nsplit, nc, s.nproj, s.d_diag.as<double>() + s.nv,
-                          1.0, C.as<z64>(), st_);
-      launch_gemm_a_c(s.beta(), s.npw, s.nproj, C.as<z64>(), {bq.as<z64>(), s.npw},
-                      ids.as<int>(), nc, s.npw, 1.0, {nullptr, 0}, nullptr, st_);
-    }
+    h_block(s, w, a.as<z64>(), bq.as<z64>(), nc);
     launch_permute_out(bq.as<z64>(), s.npw, tout.as<z64>(), s.npw, s.d_perm.as<int>(), s.npw, nc,
                        st_);
     copy_out(out + (size_t)c0 * s.npw * 2, tout.as<void>(), (size_t)nc * vb, ptr_kind, st_);
@@ -661,6 +810,7 @@ void Context::poll(uint64_t t, sth_ticket_info* info) {
   info->t_done = r->t_done;
   info->cg_iterations = r->cg_its;
   info->op_applications = r->op_apps;
+  info->op_applications_fp32 = r->op32_apps;
 }
 
 bool Context::wait(uint64_t t, double timeout) {
@@ -847,6 +997,7 @@ void Context::refill(System& s) {
   double* h_ekin = h_eps + s.nslots;
   double* h_tol = h_eps + 2 * s.nslots;
   int* h_maxit = reinterpret_cast<int*>(h_eps + 3 * s.nslots);
+  int* h_prec = reinterpret_cast<int*>(h_eps + 4 * s.nslots);
   const double** h_pp = s.h_potptr.as<const double*>();
   const long long n3 = (long long)s.N * s.N * s.N;
   const double t = now_s();
@@ -863,6 +1014,7 @@ void Context::refill(System& s) {
       h_ekin[slot] = s.ekin[v];
       h_tol[slot] = r->tol;
       h_maxit[slot] = r->maxit;
+      h_prec[slot] = r->precision == STH_MIXED ? 1 : 0;
       h_pp[slot] = r->d_dv.as<double>() + j * n3;
       fresh.push_back(slot);
       band.push_back(v);
@@ -880,6 +1032,8 @@ void Context::refill(System& s) {
                                st_));
   STH_HIP_CHECK(hipMemcpyAsync(s.ss.maxit, h_maxit, s.nslots * sizeof(int), hipMemcpyHostToDevice,
                                st_));
+  STH_HIP_CHECK(hipMemcpyAsync(s.ss.prec, h_prec, s.nslots * sizeof(int), hipMemcpyHostToDevice,
+                               st_));
   STH_HIP_CHECK(hipMemcpyAsync(s.d_potptr.as<void>(), h_pp, s.nslots * sizeof(double*),
                                hipMemcpyHostToDevice, st_));
   int* dl = upload_list(s, fresh);
@@ -887,6 +1041,7 @@ void Context::refill(System& s) {
   const int N = s.N;
   VecSet<z64> sticks{s.d_sticks.as<z64>(), (long long)N * s.nst};
   // u = FFT[dV_j(r) psi_v(r)] on the sphere, then b = -P_c u = Psi (Psi^H u) - u
+  const int hrhs = prof_begin(PH_OTHER);
   launch_copy_vecs({s.W(), (long long)s.npw}, s.vec(s.d_p), db, dl, n, s.npw, st_);
   launch_zfft_inv<double, z64>(s.g, s.cvec(s.d_p), sticks, dl, n, st_);
   launch_plane_local<double>(s.g, sticks, dl, n, nullptr, s.d_potptr.as<const double* const>(),
@@ -901,21 +1056,39 @@ void Context::refill(System& s) {
   launch_cg_init(s.g, s.cvec(s.d_b), s.vec(s.d_x), s.vec(s.d_r), s.vec(s.d_p), dl, n, s.ss.ekin,
                  s.d_part2.as<double>(), st_);
   launch_cg_init_scalars(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);
+  prof_end(hrhs, 0.0, 0.0);
 }
 
 void Context::iterate(System& s, const std::vector<int>& act, int nit) {
-  const int n = int(act.size());
-  int* dl = upload_list(s, act);
+  // slots of FP64 solves and of mixed-precision solves (FP32 inner operator)
+  // iterate as two batches; partial sums are indexed by list position, so each
+  // batch runs its whole CG step before the other starts
+  std::vector<int> lists[2];
+  for (int slot : act)
+    lists[s.slots[slot].req->precision == STH_MIXED ? 1 : 0].push_back(slot);
+  int* dl[2] = {nullptr, nullptr};
+  for (int k = 0; k < 2; ++k)
+    if (!lists[k].empty()) dl[k] = upload_list(s, lists[k]);
+  const double vb = double(s.npw) * sizeof(z64);
   for (int it = 0; it < nit; ++it) {
-    apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, true);
-    launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl, n, s.ss, st_);
-    launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl, n,
-                        s.ss, s.d_part2.as<double>(), st_);
-    launch_cg_beta(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);
-    launch_cg_update_p(s.g, s.cvec(s.d_r), s.vec(s.d_p), dl, n, s.ss, st_);
+    for (int k = 0; k < 2; ++k) {
+      const int n = int(lists[k].size());
+      if (n == 0) continue;
+      apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl[k], n, true, k == 1);
+      const int h = prof_begin(PH_CG);
+      launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl[k], n, s.ss, st_);
+      launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl[k],
+                          n, s.ss, s.d_part2.as<double>(), st_);
+      launch_cg_beta(s.d_part2.as<double>(), s.nchunk, dl[k], n, s.ss, st_);
+      launch_cg_update_p(s.g, s.cvec(s.d_r), s.vec(s.d_p), dl[k], n, s.ss, st_);
+      prof_end(h, n * 9.0 * vb + 2.0 * s.npw * 8.0, 0.0);
+    }
   }
   std::lock_guard<std::mutex> lk(mu_);
-  for (int slot : act) s.slots[slot].req->op_apps += nit;
+  for (int slot : act) {
+    s.slots[slot].req->op_apps += nit;
+    if (s.slots[slot].req->precision == STH_MIXED) s.slots[slot].req->op32_apps += nit;
+  }
 }
 
 void Context::check_and_retire(System& s, std::vector<int>& act) {
@@ -1056,6 +1229,7 @@ bool Context::step(System& s) {
   }
   finish_drho(s);
   STH_HIP_CHECK(hipStreamSynchronize(st_));
+  prof_harvest();
   return true;
 }
 

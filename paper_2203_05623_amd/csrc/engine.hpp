@@ -86,6 +86,13 @@ void gen_eig_device(Budget* b, const std::vector<double>& M, const std::vector<d
 
 struct Request;
 
+// Host-side stick maps of a sphere (see build_sticks).
+struct StickBuild {
+  std::vector<int> perm;        // caller index -> internal index
+  std::vector<int> stick_off, elem_pos, stick_i12, row_list;
+  std::vector<double> kin;
+};
+
 struct SlotHost {
   Request* req = nullptr;   // owner of the solve in this slot (null = free)
   int solve = -1;           // j * nband + band index within the request
@@ -102,6 +109,8 @@ struct System {
   DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
   DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
   DevMem d_vloc;       // [N^3] double
+  DevMem d_W32;        // FP32 copy of W (inner operator of mixed-precision solves)
+  DevMem d_vloc32;     // FP32 copy of V_loc
   DevMem d_psir;       // [nv][N^3] z64, psi_v(r) without Omega^{-1/2}
   DevMem d_eps_band;   // [nv]
   std::vector<double> eps, ekin;   // per band
@@ -151,7 +160,7 @@ struct Request {
   std::vector<int> drho_pending;     // perturbations whose bands are all finished
   int n_drho_done = 0;
   double max_resid = 0.0, t_submit = 0.0, t_start = 0.0, t_done = 0.0;
-  long long cg_its = 0, op_apps = 0;
+  long long cg_its = 0, op_apps = 0, op32_apps = 0;
   std::vector<int> iters, status;
   std::vector<double> resid, latency;
   bool failed = false;
@@ -190,10 +199,35 @@ class Context {
   void finish_drho(System& s);
   int* upload_list(System& s, const std::vector<int>& v);
   void apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                bool dots);
+                bool dots, bool fp32 = false);
+  void apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
+                  bool dots);
   void order_after(hipStream_t user);   // library stream waits for the user's stream
   void order_before(hipStream_t user);  // user's stream waits for the library stream
   void alloc_slots(System& s, int nslots);
+  StickBuild setup_geometry(System& s, const sth_system_desc& d, int nv);
+  void validate_desc(const sth_system_desc& d, bool need_psi);
+ public:
+  // H on a block of device vectors in internal order (no shift): scratch must
+  // hold n sticks; used by the valence solver.
+  struct HScratch {
+    DevMem sticks, part, C, zeros, ids;
+    int cap = 0;
+  };
+  void h_block(System& s, HScratch& w, const z64* in, z64* out, int n);
+  void h_scratch(System& s, HScratch& w, int cap);
+  Budget* budget() { return &budget_; }
+  hipStream_t stream() const { return st_; }
+
+  // kernel timing by phase (HIP events on the library stream)
+  enum { PH_ZINV, PH_PLANE, PH_ZFWD, PH_GEMM_AHB, PH_REDUCE, PH_GEMM_AC, PH_CG, PH_OTHER, NPH };
+  void profile(bool on);
+  void profile_read(double* ms, long long* n, double* bytes, double* flops);
+  int prof_begin(int phase);
+  void prof_end(int handle, double bytes, double flops);
+  void prof_harvest();   // stream must be idle
+
+ private:
 
   int device_;
   Budget budget_;
@@ -208,6 +242,18 @@ class Context {
   std::map<uint64_t, std::shared_ptr<Request>> tickets_;
   int next_sys_ = 1;
   uint64_t next_ticket_ = 1;
+
+  struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  bool prof_on_ = false;
+  std::mutex prof_mu_;
+  std::vector<ProfRec> prof_recs_;
+  std::vector<hipEvent_t> ev_pool_;
+  double prof_ms_[NPH] = {}, prof_bytes_[NPH] = {}, prof_flops_[NPH] = {};
+  long long prof_n_[NPH] = {};
 };
 
 }  // namespace sth

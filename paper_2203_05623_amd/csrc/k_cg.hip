@@ -25,6 +25,14 @@ __device__ inline double tpa(double kin, double ekin) {
   return num / (num + 16.0 * x * x * x * x);
 }
 
+// ||r||^2 at which a run of the recurrence stops and the true residual is taken:
+// the final target for FP64 solves; for the FP32 inner runs of a mixed solve a
+// fixed reduction of the residual the run started from (defect correction).
+__device__ inline double inner_target2(double final2, double start2, int prec) {
+  if (!prec) return final2;
+  return fmax(final2, MIXED_INNER_REDUCTION * MIXED_INNER_REDUCTION * start2);
+}
+
 // block-wide sum of two values, result valid in thread 0; fixed order
 __device__ inline void block_sum2(double& a, double& b) {
   __shared__ double sa[CTHR / 64], sb[CTHR / 64];
@@ -93,6 +101,7 @@ __global__ void k_cg_init_scalars(const double* part2, int nchunk, const int* sl
   s.alpha[slot] = 0.0;
   s.beta[slot] = 0.0;
   s.iters[slot] = 0;
+  s.tgt2[slot] = inner_target2(s.tol[slot] * s.tol[slot] * b, b, s.prec[slot]);
   s.status[slot] = (b > 0.0) ? SLOT_ACTIVE : (b == 0.0 ? SLOT_DONE : SLOT_NAN);
 }
 
@@ -171,7 +180,7 @@ __global__ void k_cg_beta(const double* part2, int nchunk, const int* slots, int
   if (rr != rr) {
     s.status[slot] = SLOT_NAN;
     s.beta[slot] = 0.0;
-  } else if (rr <= s.tol[slot] * s.tol[slot] * s.bnorm2[slot]) {
+  } else if (rr <= s.tgt2[slot]) {
     s.status[slot] = SLOT_CHECK;
     s.beta[slot] = 0.0;
   } else if (it >= s.maxit[slot]) {
@@ -252,6 +261,7 @@ __global__ void k_cg_check_true(const double* part2, int nchunk, const int* slot
   } else {
     s.status[slot] = SLOT_ACTIVE;
     s.rho[slot] = rz;
+    s.tgt2[slot] = inner_target2(s.tol[slot] * s.tol[slot] * s.bnorm2[slot], rr, s.prec[slot]);
   }
 }
 
@@ -288,10 +298,61 @@ __global__ void k_permute_out(const z64* src, long long ss, z64* dst, long long 
     dst[c * ds + e] = src[c * ss + perm[e]];
 }
 
+__global__ void k_z64_to_z32(const z64* s, z32* d, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    d[i] = z32{float(s[i].x), float(s[i].y)};
+}
+
 __global__ void k_to_f32(const double* s, float* d, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     d[i] = float(s[i]);
+}
+
+__global__ __launch_bounds__(CTHR) void k_row_norms(const z64* v, int n, double* out) {
+  const z64* a = v + (long long)blockIdx.x * n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int e = threadIdx.x; e < n; e += CTHR) s1 += a[e].x * a[e].x + a[e].y * a[e].y;
+  block_sum2(s1, s2);
+  if (threadIdx.x == 0) out[blockIdx.x] = s1;
+}
+
+__global__ void k_scale_rows(z64* v, int n, const double* f) {
+  z64* a = v + (long long)blockIdx.y * n;
+  const double s = f[blockIdx.y];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    a[e].x *= s;
+    a[e].y *= s;
+  }
+}
+
+__global__ __launch_bounds__(CTHR) void k_resid_precond(GridDev g, const z64* X, const z64* HX,
+                                                        const double* theta, z64* W,
+                                                        double* out) {
+  const int i = blockIdx.x;
+  const long long o = (long long)i * g.npw;
+  const double th = theta[i];
+  double s1 = 0.0, s2 = 0.0;
+  for (int e = threadIdx.x; e < g.npw; e += CTHR) {
+    const z64 x = X[o + e], h = HX[o + e];
+    const z64 r = {h.x - th * x.x, h.y - th * x.y};
+    const double d = 1.0 / (fmax(g.kin[e] - th, 0.0) + 1.0);
+    W[o + e] = z64{r.x * d, r.y * d};
+    s1 += r.x * r.x + r.y * r.y;
+  }
+  block_sum2(s1, s2);
+  if (threadIdx.x == 0) out[i] = s1;
+}
+
+__global__ void k_cols_to_rows(const z64* U, int ldu, int m0, int nm, int col0, int nc,
+                               const double* scale, z64* C) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nc * nm) return;
+  const int c = int(t / nm), m = int(t % nm);
+  const double f = scale ? scale[col0 + c] : 1.0;
+  const z64 u = U[(long long)(m0 + m) * ldu + col0 + c];
+  C[t] = z64{u.x * f, u.y * f};
 }
 
 inline dim3 vec_grid(int npw, int ncols) { return dim3(cg_chunks(npw), ncols); }
@@ -395,6 +456,40 @@ void launch_permute_out(const z64* src, long long sstride, z64* dst, long long d
   if (ncols <= 0 || n <= 0) return;
   hipLaunchKernelGGL(k_permute_out, dim3((n + 1023) / 1024, ncols), dim3(256), 0, st, src,
                      sstride, dst, dstride, perm, n);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_row_norms(const z64* v, int nvec, int n, double* out, hipStream_t st) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(k_row_norms, dim3(nvec), dim3(CTHR), 0, st, v, n, out);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_scale_rows(z64* v, int nvec, int n, const double* f, hipStream_t st) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(k_scale_rows, dim3((n + 1023) / 1024, nvec), dim3(256), 0, st, v, n, f);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_resid_precond(const GridDev& g, const z64* X, const z64* HX, const double* theta,
+                          int nvec, z64* W, double* out, hipStream_t st) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(k_resid_precond, dim3(nvec), dim3(CTHR), 0, st, g, X, HX, theta, W, out);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_cols_to_rows(const z64* U, int ldu, int m0, int nm, int col0, int nc,
+                         const double* scale, z64* C, hipStream_t st) {
+  const long long n = (long long)nc * nm;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cols_to_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U, ldu,
+                     m0, nm, col0, nc, scale, C);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_z64_to_z32(const z64* src, z32* dst, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_z64_to_z32, dim3(1024), dim3(256), 0, st, src, dst, n);
   STH_HIP_CHECK(hipGetLastError());
 }
 

@@ -1,16 +1,19 @@
-// Dense complex contractions on the FP64 matrix cores of gfx950.
+// Dense complex contractions on the matrix cores of gfx950 (FP64 and FP32).
 //
 // The projector products of the Hamiltonian (V_NL = sum |beta> D <beta|) and of
 // the valence projector P_v = sum |v><v| are tall-skinny GEMMs over the sphere
 // index: C = W^H P (reduction over npw) and Y += W C (npw output rows).  They
-// run on v_mfma_f64_16x16x4f64.  A complex product is mapped onto real MFMA by
-// interleaving the reduction index: k' = 2k + t, t = 0 for the real part and 1
-// for the imaginary part; the real A' row is the interleaved storage itself and
-// the two real B' operands are (re, im) or (im, -re) picked per lane.
+// run on v_mfma_f64_16x16x4f64 (FP64 solves) or v_mfma_f32_16x16x4f32 (the
+// inner iterations of mixed-precision solves).  A complex product is mapped
+// onto real MFMA by interleaving the reduction index: k' = 2k + t, t = 0 for
+// the real part and 1 for the imaginary part; the real A' row is the
+// interleaved storage itself and the two real B' operands are (re, im) or
+// (im, -re) picked per lane.  CG vectors stay FP64 in memory and are rounded
+// to the working precision when they are staged in LDS.
 //
-// MFMA f64 16x16x4 lane layout (64 lanes, l = lane):
+// MFMA 16x16x4 lane layout (64 lanes, l = lane), measured on gfx950:
 //   A[i][k]: i = l % 16, k = l / 16;  B[k][j]: k = l / 16, j = l % 16;
-//   D[i][j], register v: i = l / 16 + 4 v, j = l % 16   (measured on gfx950).
+//   D[i][j], register v: i = l / 16 + 4 v, j = l % 16.
 #include "errors.hpp"
 #include "kernels.hpp"
 
@@ -18,33 +21,48 @@ namespace sth {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
 
 constexpr int GT = 64;      // tile rows and columns
 constexpr int GK = 16;      // complex reduction elements per LDS stage
 constexpr int GTHR = 256;   // 4 waves, 2 x 2 arrangement of 32 x 32 sub-tiles
 
-__device__ inline d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+template <typename T, typename S>
+__device__ inline cpx<T> rnd(const S& v) { return cpx<T>{T(v.x), T(v.y)}; }
 
-// part[s][c][m] = sum_{k in chunk s} conj(A[m][k]) B_c[k]
-__global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const z64* __restrict__ A, int lda, int M,
-                                                    VecSet<const z64> B, const int* slots,
-                                                    int ncols, int K, int kchunk, z64* part) {
-  __shared__ z64 As[GT][GK + 1];
-  __shared__ z64 Bs[GT][GK + 1];
+// part[s][c][m] = sum_{k in chunk s} conj(A[m][k]) B_c[k]   (accumulated in T)
+template <typename T, typename TB>
+__global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
+                                                    VecSet<const TB> B, const int* slots,
+                                                    int ncols, int K, int kchunk, cpx<T>* part) {
+  using V4 = typename Mfma<T>::v4;
+  __shared__ cpx<T> As[GT][GK + 1];
+  __shared__ cpx<T> Bs[GT][GK + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT, s = blockIdx.z;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
-  d4 accr[2][2], acci[2][2];
+  V4 accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = d4{0, 0, 0, 0};
-  // rows of B this thread loads (fixed over the K loop)
-  const z64* brow[4];
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
+  const TB* brow[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int n = n0 + (tid + i * GTHR) / GK;
@@ -56,20 +74,20 @@ __global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const z64* __restrict__ A, i
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK, k = kb + c;
       const int m = m0 + row;
-      As[row][c] = (m < M && k < kend) ? A[(long long)m * lda + k] : z64{0, 0};
-      Bs[row][c] = (brow[i] && k < kend) ? brow[i][k] : z64{0, 0};
+      As[row][c] = (m < M && k < kend) ? A[(long long)m * lda + k] : cpx<T>{0, 0};
+      Bs[row][c] = (brow[i] && k < kend) ? rnd<T>(brow[i][k]) : cpx<T>{0, 0};
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int c = 2 * kk + (kq >> 1);
       const bool im = kq & 1;
-      double a[2], br[2], bi[2];
+      T a[2], br[2], bi[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const z64 w = As[wm * 32 + t * 16 + r16][c];
+        const cpx<T> w = As[wm * 32 + t * 16 + r16][c];
         a[t] = im ? w.y : w.x;
-        const z64 z = Bs[wn * 32 + t * 16 + r16][c];
+        const cpx<T> z = Bs[wn * 32 + t * 16 + r16][c];
         br[t] = im ? z.y : z.x;
         bi[t] = im ? -z.x : z.y;
       }
@@ -77,8 +95,8 @@ __global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const z64* __restrict__ A, i
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          accr[x][y] = mfma(a[x], br[y], accr[x][y]);
-          acci[x][y] = mfma(a[x], bi[y], acci[x][y]);
+          accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
+          acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
         }
     }
     __syncthreads();
@@ -92,42 +110,49 @@ __global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const z64* __restrict__ A, i
         const int m = m0 + wm * 32 + x * 16 + kq + 4 * v;
         const int n = n0 + wn * 32 + y * 16 + r16;
         if (m < M && n < ncols)
-          part[((long long)s * ncols + n) * M + m] = z64{accr[x][y][v], acci[x][y][v]};
+          part[((long long)s * ncols + n) * M + m] = cpx<T>{accr[x][y][v], acci[x][y][v]};
       }
 }
 
-__global__ void k_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
-                               double sgn, z64* C) {
+template <typename T>
+__global__ void k_reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M,
+                               const double* diag, double sgn, cpx<T>* C, int transpose) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)ncols * M) return;
   const int m = int(i % M);
   double re = 0.0, im = 0.0;
   for (int s = 0; s < nsplit; ++s) {
-    const z64 v = part[(long long)s * ncols * M + i];
+    const cpx<T> v = part[(long long)s * ncols * M + i];
     re += v.x;
     im += v.y;
   }
   const double d = sgn * (diag ? diag[m] : 1.0);
-  C[i] = z64{d * re, d * im};
+  const cpx<T> o = {T(d * re), T(d * im)};
+  if (transpose)
+    C[(long long)m * ncols + (i / M)] = o;
+  else
+    C[i] = o;
 }
 
 // Y_c[g] = s0 Y_c[g] + sum_m A[m][g] C[c][m]  (+ optional partial dots with dot_in)
-__global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, int lda, int M,
-                                                   const z64* __restrict__ C, VecSet<z64> Y,
+template <typename T>
+__global__ __launch_bounds__(GTHR) void k_gemm_a_c(const cpx<T>* __restrict__ A, int lda, int M,
+                                                   const cpx<T>* __restrict__ C, VecSet<z64> Y,
                                                    const int* slots, int ncols, int K, double s0,
                                                    VecSet<const z64> dot_in, double* dots) {
-  __shared__ z64 Ws[GK][GT + 1];
-  __shared__ z64 Cs[GT][GK + 1];
+  using V4 = typename Mfma<T>::v4;
+  __shared__ cpx<T> Ws[GK][GT + 1];
+  __shared__ cpx<T> Cs[GT][GK + 1];
   __shared__ double red[2][GT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = wave & 1, wn = wave >> 1;
   const int g0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
   const int kq = lane >> 4, r16 = lane & 15;
-  d4 accr[2][2], acci[2][2];
+  V4 accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = d4{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
   for (int mb = 0; mb < M; mb += GK) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -135,12 +160,12 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, in
       {
         const int mr = idx / GT, gc = idx % GT;
         const int m = mb + mr, gg = g0 + gc;
-        Ws[mr][gc] = (m < M && gg < K) ? A[(long long)m * lda + gg] : z64{0, 0};
+        Ws[mr][gc] = (m < M && gg < K) ? A[(long long)m * lda + gg] : cpx<T>{0, 0};
       }
       {
         const int nr = idx / GK, mc = idx % GK;
         const int n = n0 + nr, m = mb + mc;
-        Cs[nr][mc] = (n < ncols && m < M) ? C[(long long)n * M + m] : z64{0, 0};
+        Cs[nr][mc] = (n < ncols && m < M) ? C[(long long)n * M + m] : cpx<T>{0, 0};
       }
     }
     __syncthreads();
@@ -148,12 +173,12 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, in
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int mm = 2 * kk + (kq >> 1);
       const bool im = kq & 1;
-      double a[2], br[2], bi[2];
+      T a[2], br[2], bi[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const z64 w = Ws[mm][wg * 32 + t * 16 + r16];
+        const cpx<T> w = Ws[mm][wg * 32 + t * 16 + r16];
         a[t] = im ? w.y : w.x;
-        const z64 c = Cs[wn * 32 + t * 16 + r16][mm];
+        const cpx<T> c = Cs[wn * 32 + t * 16 + r16][mm];
         br[t] = im ? -c.y : c.x;
         bi[t] = im ? c.x : c.y;
       }
@@ -161,8 +186,8 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, in
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          accr[x][y] = mfma(a[x], br[y], accr[x][y]);
-          acci[x][y] = mfma(a[x], bi[y], acci[x][y]);
+          accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
+          acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
         }
     }
     __syncthreads();
@@ -180,9 +205,12 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, in
       for (int v = 0; v < 4; ++v) {
         const int gg = g0 + wg * 32 + x * 16 + kq + 4 * v;
         if (gg < K) {
-          z64 o = yrow[gg];
-          o.x = s0 * o.x + accr[x][y][v];
-          o.y = s0 * o.y + acci[x][y][v];
+          z64 o = {double(accr[x][y][v]), double(acci[x][y][v])};
+          if (s0 != 0.0) {   // s0 == 0 never reads Y (it may be uninitialised)
+            const z64 yo = yrow[gg];
+            o.x += s0 * yo.x;
+            o.y += s0 * yo.y;
+          }
           yrow[gg] = o;
           if (drow) {
             const z64 d = drow[gg];
@@ -212,35 +240,67 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const z64* __restrict__ A, in
   }
 }
 
+template <typename T>
+void gemm_ah_b(const cpx<T>* A, int lda, int M, VecSet<const z64> B, const int* slots, int ncols,
+               int K, int kchunk, cpx<T>* part, hipStream_t st) {
+  if (ncols <= 0 || M <= 0) return;
+  const int nsplit = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
+  hipLaunchKernelGGL((k_gemm_ah_b<T, z64>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots, ncols,
+                     K, kchunk, part);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M, const double* diag,
+                  double sgn, cpx<T>* C, hipStream_t st, bool transpose) {
+  const long long n = (long long)ncols * M;
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_reduce_parts<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     part, nsplit, ncols, M, diag, sgn, C, transpose ? 1 : 0);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void gemm_a_c(const cpx<T>* A, int lda, int M, const cpx<T>* C, VecSet<z64> Y, const int* slots,
+              int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots,
+              hipStream_t st) {
+  if (ncols <= 0) return;
+  dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
+  hipLaunchKernelGGL((k_gemm_a_c<T>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols, K,
+                     s0, dot_in, dots);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
 }  // namespace
 
 void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
                       int ncols, int K, int kchunk, z64* part, hipStream_t st) {
-  if (ncols <= 0 || M <= 0) return;
-  const int nsplit = (K + kchunk - 1) / kchunk;
-  dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
-  hipLaunchKernelGGL(k_gemm_ah_b, grid, dim3(GTHR), 0, st, A, lda, M, B, slots, ncols, K, kchunk,
-                     part);
-  STH_HIP_CHECK(hipGetLastError());
+  gemm_ah_b<double>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
+}
+void launch_gemm_ah_b(const z32* A, int lda, int M, VecSet<const z64> B, const int* slots,
+                      int ncols, int K, int kchunk, z32* part, hipStream_t st) {
+  gemm_ah_b<float>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
 }
 
 void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
-                         double sgn, z64* C, hipStream_t st) {
-  const long long n = (long long)ncols * M;
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
-                     nsplit, ncols, M, diag, sgn, C);
-  STH_HIP_CHECK(hipGetLastError());
+                         double sgn, z64* C, hipStream_t st, bool transpose) {
+  reduce_parts<double>(part, nsplit, ncols, M, diag, sgn, C, st, transpose);
+}
+void launch_reduce_parts(const z32* part, int nsplit, int ncols, int M, const double* diag,
+                         double sgn, z32* C, hipStream_t st, bool transpose) {
+  reduce_parts<float>(part, nsplit, ncols, M, diag, sgn, C, st, transpose);
 }
 
 void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
                      double* dots, hipStream_t st) {
-  if (ncols <= 0) return;
-  dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_a_c, grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols, K, s0,
-                     dot_in, dots);
-  STH_HIP_CHECK(hipGetLastError());
+  gemm_a_c<double>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
+}
+void launch_gemm_a_c(const z32* A, int lda, int M, const z32* C, VecSet<z64> Y,
+                     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
+                     double* dots, hipStream_t st) {
+  gemm_a_c<float>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
 }
 
 }  // namespace sth

@@ -60,14 +60,24 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)
 void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
                       int ncols, int K, int kchunk, z64* part, hipStream_t st);
-// C[c][m] = diag[m] * sum_s part[s][c][m]   (diag may be null -> 1)
+// C[c][m] = sgn * diag[m] * sum_s part[s][c][m]   (diag may be null -> 1);
+// transpose: written as C[m][c] instead (row m = <A_m| . >, a Gram matrix row)
 void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
-                         double sgn, z64* C, hipStream_t st);
+                         double sgn, z64* C, hipStream_t st, bool transpose = false);
 // Y_c[g] = s0 * Y_c[g] + sum_m A[m][g] C[c][m]; if dot_in, also
 // dots[c][tile] = sum_{g in tile} Re(conj(dot_in_c[g]) Y_c[g]) for 64-wide tiles of g.
 void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
                      double* dots, hipStream_t st);
+// FP32 variants (W and C in FP32, FP32 MFMA accumulation; B, Y, dots FP64 in memory)
+void launch_gemm_ah_b(const z32* A, int lda, int M, VecSet<const z64> B, const int* slots,
+                      int ncols, int K, int kchunk, z32* part, hipStream_t st);
+void launch_reduce_parts(const z32* part, int nsplit, int ncols, int M, const double* diag,
+                         double sgn, z32* C, hipStream_t st, bool transpose = false);
+void launch_gemm_a_c(const z32* A, int lda, int M, const z32* C, VecSet<z64> Y,
+                     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
+                     double* dots, hipStream_t st);
+void launch_z64_to_z32(const z64* src, z32* dst, long long n, hipStream_t st);
 inline int gemm_a_c_tiles(int K) { return (K + 63) / 64; }
 
 // ---- CG vector kernels (FP64) ----
@@ -80,10 +90,16 @@ struct SlotState {
   double* eps;       // [nslots] eps_v of the slot's band
   double* ekin;      // [nslots] kinetic energy of the slot's band (preconditioner)
   double* tol;       // [nslots] relative residual target of the slot's solve
+  double* tgt2;      // [nslots] ||r||^2 at which the recurrence stops for a true-residual check
   int* status;       // [nslots] SLOT_*
   int* iters;        // [nslots]
   int* maxit;        // [nslots]
+  int* prec;         // [nslots] 0 FP64 operator, 1 FP32 inner operator (defect correction)
 };
+// Inner target of a mixed-precision solve relative to the residual it starts from:
+// the FP32 operator is accurate to ~1e-6 relative, so each inner run reduces the
+// true residual by at most this much before the FP64 residual is recomputed.
+constexpr double MIXED_INNER_REDUCTION = 1e-5;
 enum SlotStatus : int {
   SLOT_FREE = 0,
   SLOT_ACTIVE = 1,
@@ -133,5 +149,17 @@ void launch_permute_in(const z64* src, long long sstride, z64* dst, long long ds
 void launch_permute_out(const z64* src, long long sstride, z64* dst, long long dstride,
                         const int* perm, int n, int ncols, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
+
+// ---- block operations of the valence solver (vectors contiguous, stride n) ----
+// out[i] = ||v_i||^2 for i < nvec
+void launch_row_norms(const z64* v, int nvec, int n, double* out, hipStream_t st);
+// v_i *= f[i]
+void launch_scale_rows(z64* v, int nvec, int n, const double* f, hipStream_t st);
+// R_i = HX_i - theta_i X_i, W_i = R_i / (max(T - theta_i, 0) + 1), out[i] = ||R_i||^2
+void launch_resid_precond(const GridDev& g, const z64* X, const z64* HX, const double* theta,
+                          int nvec, z64* W, double* out, hipStream_t st);
+// C[c][m] = U[(m0 + m) * ldu + col0 + c] * (scale ? scale[col0 + c] : 1), c < nc, m < nm
+void launch_cols_to_rows(const z64* U, int ldu, int m0, int nm, int col0, int nc,
+                         const double* scale, z64* C, hipStream_t st);
 
 }  // namespace sth

@@ -1,0 +1,57 @@
+"""Host-side checks of the HIP library that need no GPU: it is built, loads, and
+exports every entry point declared in include/sth.h; the ctypes structures have
+the C layout; calls without a device fail with an error code, not a crash."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+HEADER = os.path.join(ROOT, "include", "sth.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:sth_status|const char\*)\s+(sth_\w+)\s*\(", text,
+                                 re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2203_05623_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsth.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    from paper_2203_05623_amd import _lib
+    assert set(_declared()) == set(_lib.EXPORTS)
+
+
+def test_struct_layouts_match_header():
+    """Field offsets of the C structs (x86-64 SysV layout) as the binding sees them."""
+    from paper_2203_05623_amd import _lib
+    assert C.sizeof(_lib.sth_config) == 24
+    assert _lib.sth_system_desc.ptr_kind.offset == 88
+    assert C.sizeof(_lib.sth_solve_opts) == 24
+    assert _lib.sth_ticket_info.op_applications_fp32.offset == 64
+
+
+def test_no_device_is_an_error_code(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2203_05623_amd import _lib
+    with pytest.raises(_lib.SthError) as e:
+        _lib.sth_create(device=0)
+    assert e.value.code == _lib.STH_E_DEVICE
+    assert lib.sth_last_error()

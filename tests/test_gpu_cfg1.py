@@ -86,3 +86,90 @@ def test_solves_match_oracle(sth, cfg1, sys1):
     assert np.abs(S - S_ref).max() < 1e-12
     assert np.abs(lam - lam_ref).max() < 1e-10 * np.abs(lam_ref).max()
     P.sth_release_ticket(ctx, t)
+
+
+def test_valence_lobpcg_matches_dense(sth, cfg1, cfg1_dense):
+    """Device LOBPCG eigenpairs of H vs dense diagonalisation (oracle)."""
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    H_, w, V = cfg1_dense
+    e, psi, res, its = P.sth_valence(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij,
+                                     NV + 1, tol=1e-11)
+    print("valence iters", its, "residual", res)
+    assert res <= 1e-11
+    assert np.abs(e - w[:NV + 1]).max() < 1e-11
+    R = psi @ H.T - e[:, None] * psi
+    assert np.linalg.norm(R, axis=1).max() < 1e-10
+    assert np.abs(psi.conj() @ psi.T - np.eye(NV + 1)).max() < 1e-12
+
+
+def test_mixed_precision_matches_oracle(sth, cfg1, sys1):
+    """Mixed precision on the tiny crystal (FP32 FFT / H.psi / projector GEMMs inside CG,
+    FP64 residuals and defect correction): true residual 1e-8, Delta psi and chi0
+    eigenvalues within 1e-6 of the FP64 oracle."""
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    npert = cfg.npert
+    dv = workloads.dv_block(cfg, range(npert))
+    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(NV), tol=1e-8, precision=P.STH_MIXED,
+                            want_dpsi=True)
+    assert P.sth_wait(ctx, t, 120.0)
+    info = P.sth_poll(ctx, t)
+    dpsi = np.empty((npert, NV, s.npw), np.complex128)
+    P.sth_fetch_dpsi(ctx, t, dpsi)
+    iters, resid, status, lat = P.sth_fetch_stats(ctx, t, npert * NV)
+    print("mixed: iters mean", iters.mean(), "op apps", info["op_applications"],
+          "fp32", info["op_applications_fp32"], "max resid", resid.max())
+    assert np.all(status == 0) and resid.max() <= 1e-8
+    assert info["op_applications_fp32"] > 0
+    X = np.empty_like(dpsi)
+    for v in range(NV):
+        B = np.stack([oracle.rhs(s, Psi, v, dv[j]) for j in range(npert)], 1)
+        X[:, v] = oracle.solve_lu(H, Psi, eps[v], B).T
+    rel = np.linalg.norm(dpsi - X, axis=2) / np.linalg.norm(X, axis=2)
+    print("mixed dpsi max rel err", rel.max())
+    assert rel.max() < 1e-6
+    dn_ref = np.stack([oracle.drho(s, Psi, X[j]) for j in range(npert)])
+    M, S, lam = P.sth_chi0_block(ctx, t, npert)
+    lam_ref, _, _ = oracle.chi0_block(s, dv, dn_ref)
+    err = np.abs(lam - lam_ref).max() / np.abs(lam_ref).max()
+    print("mixed chi0 eigenvalue rel err", err)
+    assert err < 1e-6
+    P.sth_release_ticket(ctx, t)
+
+
+def test_solve_status_reports_maxit(sth, cfg1, sys1):
+    """Failure handling forced from the host: maxit = 3 gives per-solve MAXIT status
+    with the last iterate's residual, and the ticket still completes."""
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    dv = workloads.dv_block(cfg, range(2))
+    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(NV), tol=1e-12, maxit=3)
+    assert P.sth_wait(ctx, t, 60.0)
+    iters, resid, status, lat = P.sth_fetch_stats(ctx, t, 2 * NV)
+    assert np.all(status == P._lib.SOLVE_MAXIT)
+    assert np.all(iters == 3) and np.all(resid > 1e-12)
+    P.sth_release_ticket(ctx, t)
+
+
+def test_invalid_arguments_are_errors(sth, cfg1, sys1):
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    dv = workloads.dv_block(cfg, range(1))
+    with pytest.raises(P.SthError) as e:
+        P.sth_submit_solves(ctx, sys1, dv, np.array([0, 0]))        # repeated band
+    assert e.value.code == P._lib.STH_E_INVALID
+    with pytest.raises(P.SthError) as e:
+        P.sth_submit_solves(ctx, sys1 + 99, dv, np.arange(2))       # unknown system
+    assert e.value.code == P._lib.STH_E_NOT_FOUND
+    bad = s.miller.copy()
+    bad[1] = bad[0]                                                  # duplicate Miller index
+    with pytest.raises(P.SthError) as e:
+        P.sth_set_system(ctx, cfg.L, cfg.N, bad, s.vloc_r, s.beta, s.dij, Psi, eps)
+    assert e.value.code == P._lib.STH_E_INVALID
+    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(2), tol=1e-10)
+    assert P.sth_wait(ctx, t, 60.0)
+    P.sth_release_ticket(ctx, t)
+    with pytest.raises(P.SthError) as e:
+        P.sth_poll(ctx, t)
+    assert e.value.code == P._lib.STH_E_NOT_FOUND

@@ -1,0 +1,102 @@
+"""GPU parity at the benchmark's full size (64-atom crystal, 72^3 grid, 22,575 plane
+waves, 128 bands, 256 KB projectors), in the launch configuration bench.py uses
+(2048 slots), on sampled outputs the oracle computes one by one.
+
+The oracle's valence states come from tests/_cache (written by
+tests/golden/make_valence_cache.py, oracle only); both sides use them.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+CFG = workloads.get_config("cfg2")
+CACHE = os.path.join(ROOT, "tests", "_cache", f"cfg2_seed{CFG.seed_kb}_valence.npz")
+SAMPLES = [(0, 0), (0, 127), (1, 64), (1, 100)]
+
+
+@pytest.fixture(scope="module")
+def ref():
+    if not os.path.exists(CACHE):
+        pytest.skip(f"oracle valence cache missing: run tests/golden/make_valence_cache.py cfg2")
+    d = np.load(CACHE)
+    s = oracle.build_system("cfg2")
+    return s, d["eps"], d["psi"]
+
+
+@pytest.fixture(scope="module")
+def sth():
+    import paper_2203_05623_amd as P
+    ctx = P.sth_create(device=0, max_slots=2048)
+    yield P, ctx
+    P.sth_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def sys2(sth, ref):
+    P, ctx = sth
+    s, eps, psi = ref
+    nv = CFG.nv
+    return P.sth_set_system(ctx, CFG.L, CFG.N, s.miller, s.vloc_r, s.beta, s.dij, psi[:nv],
+                            eps[:nv])
+
+
+def test_valence_matches_oracle(sth, ref):
+    """Device LOBPCG vs the oracle's LOBPCG: eigenvalues are gauge invariant."""
+    P, ctx = sth
+    s, eps, psi = ref
+    e, v, res, its = P.sth_valence(ctx, CFG.L, CFG.N, s.miller, s.vloc_r, s.beta, s.dij,
+                                   CFG.nv + 1, tol=1e-10)
+    print("device valence: iterations", its, "residual", res)
+    assert res <= 1e-10
+    err = np.abs(e - eps[:CFG.nv + 1]).max()
+    print("eigenvalue max abs diff", err, "gap", e[CFG.nv] - e[CFG.nv - 1])
+    assert err < 1e-10
+
+
+def _oracle_dpsi(s, eps, psi, j, v, tol):
+    nv = CFG.nv
+    Psi, e = psi[:nv], eps[:nv]
+    b = oracle.rhs(s, Psi, v, workloads.dv_r(CFG, j))
+    x, it, rel, st = oracle.pcg_solve(s, Psi, e, v, b, tol=tol)
+    assert st == 0
+    return x
+
+
+@pytest.fixture(scope="module")
+def oracle_samples(ref):
+    s, eps, psi = ref
+    return {jv: _oracle_dpsi(s, eps, psi, *jv, tol=1e-12) for jv in SAMPLES}
+
+
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6)])
+def test_sampled_solves_match_oracle(sth, ref, sys2, oracle_samples, precision, tol, bound):
+    P, ctx = sth
+    s, eps, psi = ref
+    npert = 2
+    dv = workloads.dv_block(CFG, range(npert))
+    prec = P.STH_FP64 if precision == "fp64" else P.STH_MIXED
+    t = P.sth_submit_solves(ctx, sys2, dv, np.arange(CFG.nv), tol=tol, precision=prec,
+                            want_dpsi=True)
+    assert P.sth_wait(ctx, t, 300.0)
+    info = P.sth_poll(ctx, t)
+    iters, resid, status, lat = P.sth_fetch_stats(ctx, t, npert * CFG.nv)
+    print(precision, "iters mean/max", iters.mean(), iters.max(), "max resid", resid.max(),
+          "op apps", info["op_applications"], "fp32", info["op_applications_fp32"])
+    assert np.all(status == 0) and resid.max() <= tol
+    dpsi = np.empty((npert, CFG.nv, s.npw), np.complex128)
+    P.sth_fetch_dpsi(ctx, t, dpsi)
+    for (j, v), x in oracle_samples.items():
+        rel = np.linalg.norm(dpsi[j, v] - x) / np.linalg.norm(x)
+        print(precision, "sample", (j, v), "rel err", rel)
+        assert rel < bound
+    # every solution is orthogonal to the valence manifold
+    ov = np.abs(np.einsum("vg,jwg->jwv", psi[:CFG.nv].conj(), dpsi)).max()
+    assert ov < 1e-10 * np.abs(dpsi).max() * np.sqrt(s.npw)
+    P.sth_release_ticket(ctx, t)
