@@ -74,6 +74,92 @@ def cpu_baseline(name: str, tol: float, nsample: int):
                       f"(one thread each), valence states from the oracle cache"}
 
 
+# ---------------------------------------------------------------- served mode
+def served(args):
+    """Poisson stream of solve requests over systems of different grid sizes (one
+    ΔV block of 32 perturbations x all bands per request), mixed precision.  The
+    arrival rate is 0.7 x the measured saturation request rate; prints one JSON
+    line with request and solve latency percentiles."""
+    import torch  # noqa: F401  (device runtime of the process)
+    import paper_2203_05623_amd as P
+
+    names = args.served_systems.split(",")
+    ctx = P.sth_create(device=0, max_slots=args.slots)
+    systems = {}
+    for name in names:
+        cfg = workloads.get_config(name)
+        miller = workloads.miller_sphere(cfg.M2)
+        vloc = workloads.vloc_r(cfg)
+        beta = workloads.beta_projectors(cfg, miller)
+        dij = workloads.dij(cfg)
+        t0 = time.perf_counter()
+        eps, psi, res, its = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, cfg.nv + 1,
+                                           tol=1e-10)
+        sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
+                               eps[:cfg.nv])
+        import torch as _t
+        dv = _t.from_numpy(workloads.dv_block(cfg, range(cfg.npert))).to("cuda:0")
+        systems[name] = dict(cfg=cfg, sid=sid, dv=dv, gap=float(eps[cfg.nv] - eps[cfg.nv - 1]),
+                             setup_s=time.perf_counter() - t0)
+        print(f"{name}: setup {systems[name]['setup_s']:.1f} s, gap {systems[name]['gap']:.4f} Ha",
+              file=sys.stderr, flush=True)
+    prec = P.STH_MIXED if args.precision == "mixed" else P.STH_FP64
+
+    def submit(name):
+        s = systems[name]
+        return P.sth_submit_solves(ctx, s["sid"], s["dv"], np.arange(s["cfg"].nv), tol=args.tol,
+                                   precision=prec)
+
+    rng = np.random.default_rng(4)
+    # saturation: a burst of requests, throughput = requests / makespan
+    burst = [names[i % len(names)] for i in range(2 * len(names))]
+    t0 = time.perf_counter()
+    tickets = [submit(n) for n in burst]
+    for t in tickets:
+        P.sth_wait(ctx, t, 3600.0)
+        P.sth_release_ticket(ctx, t)
+    sat = len(burst) / (time.perf_counter() - t0)
+    rate = 0.7 * sat
+    print(f"saturation {sat:.3f} req/s, arrival rate {rate:.3f} req/s", file=sys.stderr, flush=True)
+    nreq = args.served_requests
+    warm = max(1, nreq // 10)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq + warm))
+    choice = rng.integers(len(names), size=nreq + warm)
+    live = []
+    t_start = time.perf_counter()
+    for k in range(nreq + warm):
+        now = time.perf_counter() - t_start
+        if arrivals[k] > now:
+            time.sleep(arrivals[k] - now)
+        live.append((k, names[choice[k]], submit(names[choice[k]])))
+    req_lat, solve_lat, done_solves = [], [], 0
+    for k, name, t in live:
+        P.sth_wait(ctx, t, 3600.0)
+        info = P.sth_poll(ctx, t)
+        if k >= warm:
+            n = info["n_total"]
+            _, _, st, lat = P.sth_fetch_stats(ctx, t, n)
+            req_lat.append(info["t_done"] - info["t_submit"])
+            solve_lat.append(lat)
+            done_solves += n
+        P.sth_release_ticket(ctx, t)
+    span = time.perf_counter() - t_start
+    P.sth_destroy(ctx)
+    req_lat = np.array(req_lat) * 1e3
+    solve_lat = np.concatenate(solve_lat) * 1e3
+    out = {"mode": "served", "systems": {n: {"grid": s["cfg"].N, "bands": s["cfg"].nv,
+                                              "npw": len(workloads.miller_sphere(s["cfg"].M2)),
+                                              "gap_Ha": s["gap"]} for n, s in systems.items()},
+           "precision": args.precision, "tol": args.tol, "requests": nreq, "warmup_requests": warm,
+           "saturation_req_per_s": sat, "arrival_rate_req_per_s": rate,
+           "solves_per_s": done_solves / span,
+           "request_latency_ms": {"p50": float(np.percentile(req_lat, 50)),
+                                  "p99": float(np.percentile(req_lat, 99))},
+           "solve_latency_ms": {"p50": float(np.percentile(solve_lat, 50)),
+                                "p99": float(np.percentile(solve_lat, 99))}}
+    print(json.dumps(out))
+
+
 # ---------------------------------------------------------------- GPU run
 def main():
     ap = argparse.ArgumentParser()
@@ -87,12 +173,21 @@ def main():
     ap.add_argument("--slots", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--served", action="store_true",
+                    help="served mode: Poisson request stream over several systems")
+    ap.add_argument("--served-systems", default="cfg4a,cfg4b")
+    ap.add_argument("--served-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for "
               f"--gpus {args.gpus}); the per-GPU work would be sharded by perturbation.",
               file=sys.stderr)
         sys.exit(2)
+    if args.served:
+        served(args)
+        return
     cfg = workloads.get_config(args.config)
     npert = args.npert or cfg.npert
     nsolves = npert * cfg.nv
@@ -103,6 +198,14 @@ def main():
 
     import torch
     import paper_2203_05623_amd as P
+
+    if args.calib_copy:
+        # a plain copy kernel of known size: reads and writes 1 GiB each
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     miller = workloads.miller_sphere(cfg.M2)
     vloc = workloads.vloc_r(cfg)

@@ -116,6 +116,8 @@ typedef struct {
   long long cg_iterations;  /* sum of CG iterations over finished solves */
   long long op_applications;/* operator applications incl. true-residual checks */
   long long op_applications_fp32; /* of which with the FP32 inner operator (STH_MIXED) */
+  long long graph_replays;  /* hipGraph replays of captured CG iterations on the ticket's
+                               system so far (steady state with every slot busy) */
 } sth_ticket_info;
 
 /* Creates a context on cfg->device (cfg may be NULL for defaults).  Starts the
@@ -132,6 +134,21 @@ sth_status sth_destroy(sth_ctx* ctx);
  * a minimal slot pool does not fit the budget.  nv >= 1 is required. */
 sth_status sth_set_system(sth_ctx* ctx, const sth_system_desc* desc, void* stream,
                           int32_t* system_id);
+
+/* Shape and tuning of a resident system.  The autotuner times, once per system
+ * (or reads from the JSON-lines cache named by the environment variable
+ * STH_TUNE_CACHE), each radix plan of the FFT kernels in FP64 and FP32 and the
+ * split-K chunk of the projector GEMM on the system's real slot batch, and keeps
+ * the fastest. */
+typedef struct {
+  int npw, nsticks, nslots, nv, nproj;
+  int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
+  int gemm_kchunk;                    /* split-K chunk of C = W^H P */
+  double tune_ms[8];                  /* timings behind the choice (plan0/1 fp64, plan0/1
+                                         fp32, kchunk candidates 0..2), ms per launch set */
+  int tuned_from_cache;
+} sth_system_info;
+sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 
 /* Frees a system; its unfinished tickets fail with STH_E_NOT_FOUND afterwards. */
 sth_status sth_release_system(sth_ctx* ctx, int32_t system_id);

@@ -25,7 +25,7 @@ SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
            "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
            "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
-           "sth_profile", "sth_profile_read", "sth_last_error"]
+           "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_last_error"]
 PHASES = ["zfft_inv", "plane", "zfft_fwd", "gemm_ah_b", "reduce", "gemm_a_c", "cg", "rhs_retire"]
 
 
@@ -51,7 +51,14 @@ class sth_ticket_info(C.Structure):
                 ("n_converged", C.c_int), ("max_rel_resid", C.c_double),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
                 ("cg_iterations", C.c_longlong), ("op_applications", C.c_longlong),
-                ("op_applications_fp32", C.c_longlong)]
+                ("op_applications_fp32", C.c_longlong), ("graph_replays", C.c_longlong)]
+
+
+class sth_system_info(C.Structure):
+    _fields_ = [("npw", C.c_int), ("nsticks", C.c_int), ("nslots", C.c_int), ("nv", C.c_int),
+                ("nproj", C.c_int), ("fft_plan_fp64", C.c_int), ("fft_plan_fp32", C.c_int),
+                ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 8),
+                ("tuned_from_cache", C.c_int)]
 
 
 class SthError(RuntimeError):
@@ -84,6 +91,7 @@ def load():
         "sth_release_ticket": [vp, u64],
         "sth_profile": [vp, C.c_int],
         "sth_profile_read": [vp, vp, vp, vp, vp],
+        "sth_system_info_get": [vp, i32, C.POINTER(sth_system_info)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -301,6 +309,14 @@ def sth_profile_read(ctx):
     _check(lib().sth_profile_read(ctx, ms.ctypes.data, n.ctypes.data, b.ctypes.data,
                                   f.ctypes.data))
     return {PHASES[i]: (float(ms[i]), int(n[i]), float(b[i]), float(f[i])) for i in range(8)}
+
+
+def sth_system_info_get(ctx, system_id):
+    info = sth_system_info()
+    _check(lib().sth_system_info_get(ctx, system_id, C.byref(info)))
+    out = {k: getattr(info, k) for k, _ in sth_system_info._fields_}
+    out["tune_ms"] = list(info.tune_ms)
+    return out
 
 
 def sth_last_error():

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsth.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_fft.hip", "k_gemm.hip", "k_cg.hip", "k_eig.hip", "engine.cpp", "valence.cpp",
+SOURCES = ["k_fft.hip", "k_gemm.hip", "k_cg.hip", "k_eig.hip", "engine.cpp", "valence.cpp", "tune.cpp",
            "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -92,6 +92,13 @@ sth_status sth_set_system(sth_ctx* ctx, const sth_system_desc* desc, void* strea
   });
 }
 
+sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info) {
+  return guard([&] {
+    need(info != nullptr, "info");
+    ctx_of(ctx)->system_info(system_id, info);
+  });
+}
+
 sth_status sth_release_system(sth_ctx* ctx, int32_t system_id) {
   return guard([&] { ctx_of(ctx)->release_system(system_id); });
 }

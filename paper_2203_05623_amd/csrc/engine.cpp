@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <set>
@@ -142,6 +143,8 @@ Context::Context(const sth_config& cfg)
   size_t lim = cfg.hbm_budget_bytes ? cfg.hbm_budget_bytes : size_t(0.9 * double(fr));
   budget_.set_limit(lim);
   STH_HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+  // STH_GRAPHS=0 turns the captured-iteration replay off (direct launches)
+  if (const char* e = std::getenv("STH_GRAPHS")) use_graphs_ = std::atoi(e) != 0;
   server_ = std::thread([this] { server_loop(); });
 }
 
@@ -279,6 +282,13 @@ void Context::alloc_slots(System& s, int nslots) {
                    dd + 5 * nslots, dd + 6 * nslots, dd + 7 * nslots, dd + 8 * nslots,
                    di, di + nslots, di + 2 * nslots, di + 3 * nslots};
   s.d_potptr = DevMem(&budget_, (size_t)nslots * sizeof(double*));
+  {
+    std::vector<int> id(nslots);
+    std::iota(id.begin(), id.end(), 0);
+    s.d_ident = upload(&budget_, id, st_);
+    STH_HIP_CHECK(hipStreamSynchronize(st_));
+  }
+  prepare_fft_kernels(s.N);
   const int arena = 16 * nslots + 4 * std::max(s.nv, 1) + 4096;
   s.d_lists = DevMem(&budget_, (size_t)arena * sizeof(int));
   s.h_lists = HostMem((size_t)arena * sizeof(int));
@@ -433,6 +443,7 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   while (ns > 64 && !budget_.fits(resident + (size_t)ns * per_slot + (budget_.limit() / 4)))
     ns /= 2;
   alloc_slots(s, ns);
+  autotune(s);
 
   // orthonormality of psi_v on the device: G = Psi^H Psi
   {
@@ -811,6 +822,8 @@ void Context::poll(uint64_t t, sth_ticket_info* info) {
   info->cg_iterations = r->cg_its;
   info->op_applications = r->op_apps;
   info->op_applications_fp32 = r->op32_apps;
+  const auto sit = systems_.find(r->sys_id);   // the system may have been released
+  info->graph_replays = sit != systems_.end() ? sit->second->graph_replays : 0;
 }
 
 bool Context::wait(uint64_t t, double timeout) {
@@ -1059,6 +1072,21 @@ void Context::refill(System& s) {
   prof_end(hrhs, 0.0, 0.0);
 }
 
+// One CG iteration on the listed slots: q = A p (FP64 or FP32 operator) with
+// <p, q> partials, alpha, x/r update with <r, K r> and ||r||^2, beta and the
+// convergence test, p = K r + beta p.
+void Context::cg_step(System& s, const int* dl, int n, bool fp32) {
+  const double vb = double(s.npw) * sizeof(z64);
+  apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, true, fp32);
+  const int h = prof_begin(PH_CG);
+  launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl, n, s.ss, st_);
+  launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl, n, s.ss,
+                      s.d_part2.as<double>(), st_);
+  launch_cg_beta(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);
+  launch_cg_update_p(s.g, s.cvec(s.d_r), s.vec(s.d_p), dl, n, s.ss, st_);
+  prof_end(h, n * 9.0 * vb + 2.0 * s.npw * 8.0, 0.0);
+}
+
 void Context::iterate(System& s, const std::vector<int>& act, int nit) {
   // slots of FP64 solves and of mixed-precision solves (FP32 inner operator)
   // iterate as two batches; partial sums are indexed by list position, so each
@@ -1066,23 +1094,31 @@ void Context::iterate(System& s, const std::vector<int>& act, int nit) {
   std::vector<int> lists[2];
   for (int slot : act)
     lists[s.slots[slot].req->precision == STH_MIXED ? 1 : 0].push_back(slot);
-  int* dl[2] = {nullptr, nullptr};
-  for (int k = 0; k < 2; ++k)
-    if (!lists[k].empty()) dl[k] = upload_list(s, lists[k]);
-  const double vb = double(s.npw) * sizeof(z64);
-  for (int it = 0; it < nit; ++it) {
-    for (int k = 0; k < 2; ++k) {
-      const int n = int(lists[k].size());
-      if (n == 0) continue;
-      apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl[k], n, true, k == 1);
-      const int h = prof_begin(PH_CG);
-      launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl[k], n, s.ss, st_);
-      launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl[k],
-                          n, s.ss, s.d_part2.as<double>(), st_);
-      launch_cg_beta(s.d_part2.as<double>(), s.nchunk, dl[k], n, s.ss, st_);
-      launch_cg_update_p(s.g, s.cvec(s.d_r), s.vec(s.d_p), dl[k], n, s.ss, st_);
-      prof_end(h, n * 9.0 * vb + 2.0 * s.npw * 8.0, 0.0);
+  // steady state: every slot holds a solve of one precision -> replay the
+  // captured graph of nit iterations over the identity list (kernels skip slots
+  // that are no longer ACTIVE).  The per-kernel profiler needs direct launches.
+  const int kall = lists[0].empty() ? 1 : (lists[1].empty() ? 0 : -1);
+  if (use_graphs_ && !prof_on_ && kall >= 0 && int(act.size()) == s.nslots) {
+    if (!s.graph[kall] || s.graph_nit[kall] != nit) {
+      if (s.graph[kall]) STH_HIP_CHECK(hipGraphExecDestroy(s.graph[kall]));
+      s.graph[kall] = nullptr;
+      hipGraph_t gr = nullptr;
+      STH_HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+      for (int it = 0; it < nit; ++it) cg_step(s, s.d_ident.as<int>(), s.nslots, kall == 1);
+      STH_HIP_CHECK(hipStreamEndCapture(st_, &gr));
+      STH_HIP_CHECK(hipGraphInstantiate(&s.graph[kall], gr, nullptr, nullptr, 0));
+      STH_HIP_CHECK(hipGraphDestroy(gr));
+      s.graph_nit[kall] = nit;
     }
+    STH_HIP_CHECK(hipGraphLaunch(s.graph[kall], st_));
+    s.graph_replays += 1;
+  } else {
+    int* dl[2] = {nullptr, nullptr};
+    for (int k = 0; k < 2; ++k)
+      if (!lists[k].empty()) dl[k] = upload_list(s, lists[k]);
+    for (int it = 0; it < nit; ++it)
+      for (int k = 0; k < 2; ++k)
+        if (!lists[k].empty()) cg_step(s, dl[k], int(lists[k].size()), k == 1);
   }
   std::lock_guard<std::mutex> lk(mu_);
   for (int slot : act) {

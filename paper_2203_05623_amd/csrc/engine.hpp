@@ -130,6 +130,19 @@ struct System {
   DevMem d_drho_sticks;      // [nband_max][N][nst] z64 scratch of the density response
   int drho_nb = 0;
 
+  // hipGraph of `graph_nit` CG iterations over every slot (steady state), one per
+  // operator precision; captured on first use, replayed each check period
+  double tune_ms[8] = {};          // autotuner timings (see sth_system_info)
+  int tuned_from_cache = 0;
+  DevMem d_ident;                  // [nslots] 0..nslots-1
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_nit[2] = {0, 0};
+  long long graph_replays = 0;
+  ~System() {
+    for (auto& gx : graph)
+      if (gx) (void)hipGraphExecDestroy(gx);
+  }
+
   std::deque<std::shared_ptr<Request>> waiting;   // submitted, not admitted
   std::vector<std::shared_ptr<Request>> running;  // admitted, unfinished
 
@@ -186,8 +199,10 @@ class Context {
   void fetch_stats(uint64_t t, int32_t* iters, double* resid, int32_t* status, double* lat);
   void chi0_block(uint64_t t, double* M, double* S, double* lam);
   void release_ticket(uint64_t t);
+  void system_info(int id, sth_system_info* info);
 
  private:
+  void autotune(System& s);
   std::shared_ptr<Request> find(uint64_t t);
   System& sys(int id);
   void server_loop();
@@ -195,6 +210,7 @@ class Context {
   void admit(System& s);
   void refill(System& s);
   void iterate(System& s, const std::vector<int>& act, int nit);
+  void cg_step(System& s, const int* dl, int n, bool fp32);   // one CG iteration (launches only)
   void check_and_retire(System& s, std::vector<int>& act);
   void finish_drho(System& s);
   int* upload_list(System& s, const std::vector<int>& v);
@@ -232,6 +248,7 @@ class Context {
   int device_;
   Budget budget_;
   int max_slots_, check_every_;
+  bool use_graphs_ = true;
   hipStream_t st_ = nullptr;
   std::mutex mu_;        // tickets, systems map, request progress
   std::mutex gpu_mu_;    // serialises device work of API calls and the server

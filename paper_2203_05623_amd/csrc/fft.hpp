@@ -206,33 +206,27 @@ struct LdsFFT {
   }
 };
 
-// Radix plans per length (first radix applied first).
-template <int N>
+// Radix plans per length (first radix applied first); two plans per length,
+// chosen per system and precision by the autotuner (plan 0 is the default).
+template <int N, int P>
 struct RadixPlan;
-template <>
-struct RadixPlan<24> {
-  template <typename T, int SIGN, int NTHR, int NFFTMAX>
-  using fft = LdsFFT<T, 24, SIGN, NTHR, NFFTMAX, 1, 8, 3>;
-};
-template <>
-struct RadixPlan<48> {
-  template <typename T, int SIGN, int NTHR, int NFFTMAX>
-  using fft = LdsFFT<T, 48, SIGN, NTHR, NFFTMAX, 1, 16, 3>;
-};
-template <>
-struct RadixPlan<72> {
-  template <typename T, int SIGN, int NTHR, int NFFTMAX>
-  using fft = LdsFFT<T, 72, SIGN, NTHR, NFFTMAX, 1, 8, 9>;
-};
-template <>
-struct RadixPlan<96> {
-  template <typename T, int SIGN, int NTHR, int NFFTMAX>
-  using fft = LdsFFT<T, 96, SIGN, NTHR, NFFTMAX, 1, 16, 6>;
-};
-template <>
-struct RadixPlan<144> {
-  template <typename T, int SIGN, int NTHR, int NFFTMAX>
-  using fft = LdsFFT<T, 144, SIGN, NTHR, NFFTMAX, 1, 16, 9>;
-};
+#define STH_RADIX_PLAN(NV, PV, ...)                                  \
+  template <>                                                        \
+  struct RadixPlan<NV, PV> {                                         \
+    template <typename T, int SIGN, int NTHR, int NFFTMAX>           \
+    using fft = LdsFFT<T, NV, SIGN, NTHR, NFFTMAX, 1, __VA_ARGS__>;  \
+  };
+STH_RADIX_PLAN(24, 0, 8, 3)
+STH_RADIX_PLAN(24, 1, 4, 6)
+STH_RADIX_PLAN(48, 0, 16, 3)
+STH_RADIX_PLAN(48, 1, 8, 6)
+STH_RADIX_PLAN(72, 0, 8, 9)
+STH_RADIX_PLAN(72, 1, 9, 8)
+STH_RADIX_PLAN(96, 0, 16, 6)
+STH_RADIX_PLAN(96, 1, 6, 16)
+STH_RADIX_PLAN(144, 0, 16, 9)
+STH_RADIX_PLAN(144, 1, 9, 16)
+#undef STH_RADIX_PLAN
+constexpr int kRadixPlans = 2;
 
 }  // namespace sth

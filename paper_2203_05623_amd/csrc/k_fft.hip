@@ -13,6 +13,8 @@
 //              potential, transformed forward and gathered back.
 //   zfft_fwd   z-sticks -> sphere: forward transform along axis 0, 1/N^3, the
 //              sphere components extracted, kinetic and shift terms fused.
+// Every kernel is instantiated for each radix plan of its length; the plan used
+// is chosen per system and precision (GridDev::plan, set by the autotuner).
 #include "errors.hpp"
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -22,6 +24,7 @@ namespace sth {
 namespace {
 
 constexpr int ZTHR = 256;
+constexpr int PTHR = 512;    // threads of a plane workgroup
 
 // sticks per workgroup in the z-stick kernels: 64, halved while the LDS tile
 // would exceed 40 KB
@@ -29,7 +32,6 @@ template <int N, typename T>
 constexpr int zsticks() {
   return (64 * (N + 1) * int(sizeof(cpx<T>)) > 40960) ? 32 : 64;
 }
-constexpr int PTHR = 256;    // threads of a plane workgroup
 
 template <typename T>
 __device__ inline const cpx<T>* twiddles(const GridDev& g);
@@ -48,16 +50,25 @@ struct real_of<cpx<T>> {
   using type = T;
 };
 
+// Twiddles (and, for planes, the active-row list) are staged in LDS once per
+// workgroup: the butterflies read them there instead of from global memory.
+template <typename T, int NTHR>
+__device__ inline void stage_twiddles(cpx<T>* dst, const cpx<T>* src, int n) {
+  for (int i = threadIdx.x; i < n; i += NTHR) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------ z sticks
-template <int N, typename T, typename Tin>
+template <int N, int P, typename T, typename Tin>
 __global__ __launch_bounds__(ZTHR) void k_zfft_inv(GridDev g, VecSet<const Tin> in,
                                                     VecSet<cpx<T>> sticks, const int* slots) {
   constexpr int NPAD = N + 1;
   constexpr int ZS = zsticks<N, T>();
   __shared__ cpx<T> buf[ZS * NPAD];
+  __shared__ cpx<T> tw[N];
   const int slot = slots[blockIdx.y];
   const int s0 = blockIdx.x * ZS;
   const int ns = min(ZS, g.nst - s0);
+  stage_twiddles<T, ZTHR>(tw, twiddles<T>(g), N);
   for (int i = threadIdx.x; i < ZS * NPAD; i += ZTHR) buf[i] = cpx<T>{T(0), T(0)};
   __syncthreads();
   const Tin* src = in.base + slot * in.stride;
@@ -68,8 +79,8 @@ __global__ __launch_bounds__(ZTHR) void k_zfft_inv(GridDev g, VecSet<const Tin> 
     buf[st * NPAD + i0] = cvt<T>(src[e]);
   }
   __syncthreads();
-  RadixPlan<N>::template fft<T, +1, ZTHR, ZS>::run(
-      buf, ns, 1, [](int f) { return f * NPAD; }, twiddles<T>(g));
+  RadixPlan<N, P>::template fft<T, +1, ZTHR, ZS>::run(
+      buf, ns, 1, [](int f) { return f * NPAD; }, tw);
   cpx<T>* dst = sticks.base + slot * sticks.stride;
   for (int t = threadIdx.x; t < N * ns; t += ZTHR) {
     const int i0 = t / ns, st = t - i0 * ns;
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(ZTHR) void k_zfft_inv(GridDev g, VecSet<const Tin> 
   }
 }
 
-template <int N, typename T, typename Tout>
+template <int N, int P, typename T, typename Tout>
 __global__ __launch_bounds__(ZTHR) void k_zfft_fwd(GridDev g, VecSet<const cpx<T>> sticks,
                                                     VecSet<Tout> out, const int* slots,
                                                     int mode, VecSet<const Tout> pin,
@@ -85,17 +96,19 @@ __global__ __launch_bounds__(ZTHR) void k_zfft_fwd(GridDev g, VecSet<const cpx<T
   constexpr int NPAD = N + 1;
   constexpr int ZS = zsticks<N, T>();
   __shared__ cpx<T> buf[ZS * NPAD];
+  __shared__ cpx<T> tw[N];
   const int slot = slots[blockIdx.y];
   const int s0 = blockIdx.x * ZS;
   const int ns = min(ZS, g.nst - s0);
+  stage_twiddles<T, ZTHR>(tw, twiddles<T>(g), N);
   const cpx<T>* src = sticks.base + slot * sticks.stride;
   for (int t = threadIdx.x; t < N * ns; t += ZTHR) {
     const int i0 = t / ns, st = t - i0 * ns;
     buf[st * NPAD + i0] = src[(long long)i0 * g.nst + s0 + st];
   }
   __syncthreads();
-  RadixPlan<N>::template fft<T, -1, ZTHR, ZS>::run(
-      buf, ns, 1, [](int f) { return f * NPAD; }, twiddles<T>(g));
+  RadixPlan<N, P>::template fft<T, -1, ZTHR, ZS>::run(
+      buf, ns, 1, [](int f) { return f * NPAD; }, tw);
   const double inv_n3 = 1.0 / (double(N) * N * N);
   Tout* dst = out.base + slot * out.stride;
   const int e0 = g.stick_off[s0], e1 = g.stick_off[s0 + ns];
@@ -118,113 +131,140 @@ __global__ __launch_bounds__(ZTHR) void k_zfft_fwd(GridDev g, VecSet<const cpx<T
 }
 
 // ------------------------------------------------------------------ planes
-// LDS tile [i1][i2] with row pitch N + 1.  Rows transformed along i2 are the
-// active rows only (the others are zero before the i1 transform).
+// Dynamic LDS of a plane workgroup: the N x (N + 1) tile [i1][i2], the N
+// twiddles and the active-row list.  Rows transformed along i2 are the active
+// rows only (the others are zero before the i1 transform).
 template <int N, typename T>
-__device__ inline void plane_inverse(cpx<T>* pl, const GridDev& g, const cpx<T>* tw) {
-  constexpr int NP = N + 1;
-  const int* rows = g.row_list;
-  RadixPlan<N>::template fft<T, +1, PTHR, N>::run(
-      pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, tw);
-  RadixPlan<N>::template fft<T, +1, PTHR, N>::run(pl, N, NP, [](int f) { return f; }, tw);
-}
+struct PlaneLds {
+  static constexpr int NP = N + 1;
+  cpx<T>* pl;
+  cpx<T>* tw;
+  int* rows;
+  __device__ explicit PlaneLds(unsigned char* raw)
+      : pl(reinterpret_cast<cpx<T>*>(raw)),
+        tw(reinterpret_cast<cpx<T>*>(raw) + N * NP),
+        rows(reinterpret_cast<int*>(reinterpret_cast<cpx<T>*>(raw) + N * NP + N)) {}
+  static constexpr size_t bytes() {
+    return size_t(N) * NP * sizeof(cpx<T>) + N * sizeof(cpx<T>) + N * sizeof(int);
+  }
+};
 
 template <int N, typename T>
-__device__ inline void plane_forward(cpx<T>* pl, const GridDev& g, const cpx<T>* tw) {
-  constexpr int NP = N + 1;
-  const int* rows = g.row_list;
-  RadixPlan<N>::template fft<T, -1, PTHR, N>::run(pl, N, NP, [](int f) { return f; }, tw);
-  RadixPlan<N>::template fft<T, -1, PTHR, N>::run(
-      pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, tw);
+__device__ inline void plane_stage(PlaneLds<N, T>& L, const GridDev& g) {
+  stage_twiddles<T, PTHR>(L.tw, twiddles<T>(g), N);
+  for (int i = threadIdx.x; i < g.nrow; i += PTHR) L.rows[i] = g.row_list[i];
 }
 
-template <int N, typename T>
-__device__ inline void plane_scatter(cpx<T>* pl, const GridDev& g, const cpx<T>* row) {
+template <int N, int P, typename T>
+__device__ inline void plane_inverse(PlaneLds<N, T>& L, const GridDev& g) {
   constexpr int NP = N + 1;
-  for (int i = threadIdx.x; i < N * NP; i += PTHR) pl[i] = cpx<T>{T(0), T(0)};
+  const int* rows = L.rows;
+  RadixPlan<N, P>::template fft<T, +1, PTHR, N>::run(
+      L.pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, L.tw);
+  RadixPlan<N, P>::template fft<T, +1, PTHR, N>::run(L.pl, N, NP, [](int f) { return f; },
+                                                     L.tw);
+}
+
+template <int N, int P, typename T>
+__device__ inline void plane_forward(PlaneLds<N, T>& L, const GridDev& g) {
+  constexpr int NP = N + 1;
+  const int* rows = L.rows;
+  RadixPlan<N, P>::template fft<T, -1, PTHR, N>::run(L.pl, N, NP, [](int f) { return f; },
+                                                     L.tw);
+  RadixPlan<N, P>::template fft<T, -1, PTHR, N>::run(
+      L.pl, g.nrow, 1, [rows](int f) { return rows[f] * NP; }, L.tw);
+}
+
+// zero the tile, scatter the stick values of one plane (row of the stick array)
+template <int N, typename T>
+__device__ inline void plane_scatter(PlaneLds<N, T>& L, const GridDev& g, const cpx<T>* row) {
+  constexpr int NP = N + 1;
+  for (int i = threadIdx.x; i < N * NP; i += PTHR) L.pl[i] = cpx<T>{T(0), T(0)};
   __syncthreads();
   for (int s = threadIdx.x; s < g.nst; s += PTHR) {
     const int p = g.stick_i12[s];
     const int i1 = p / N, i2 = p - (p / N) * N;
-    pl[i1 * NP + i2] = row[s];
+    L.pl[i1 * NP + i2] = row[s];
   }
   __syncthreads();
 }
 
-template <int N, typename T>
+template <int N, int P, typename T>
 __global__ __launch_bounds__(PTHR) void k_plane_local(GridDev g, VecSet<cpx<T>> sticks,
                                                        const int* slots, const T* pot,
                                                        const T* const* pot_ptr) {
   constexpr int NP = N + 1;
   extern __shared__ unsigned char smem_raw[];
-  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  PlaneLds<N, T> L(smem_raw);
   const int slot = slots[blockIdx.y];
   const int i0 = blockIdx.x;
   cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
-  const cpx<T>* tw = twiddles<T>(g);
-  plane_scatter<N, T>(pl, g, row);
-  plane_inverse<N, T>(pl, g, tw);
+  plane_stage<N, T>(L, g);
+  plane_scatter<N, T>(L, g, row);
+  plane_inverse<N, P, T>(L, g);
   const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
   for (int e = threadIdx.x; e < N * N; e += PTHR) {
     const int i1 = e / N, i2 = e - (e / N) * N;
     const T v = V[e];
-    cpx<T>& c = pl[i1 * NP + i2];
+    cpx<T>& c = L.pl[i1 * NP + i2];
     c.x *= v;
     c.y *= v;
   }
   __syncthreads();
-  plane_forward<N, T>(pl, g, tw);
+  plane_forward<N, P, T>(L, g);
   for (int s = threadIdx.x; s < g.nst; s += PTHR) {
     const int p = g.stick_i12[s];
     const int i1 = p / N, i2 = p - (p / N) * N;
-    row[s] = pl[i1 * NP + i2];
+    row[s] = L.pl[i1 * NP + i2];
   }
 }
 
-template <int N, typename T>
+template <int N, int P, typename T>
 __global__ __launch_bounds__(PTHR) void k_plane_to_grid(GridDev g, VecSet<const cpx<T>> sticks,
                                                          VecSet<cpx<T>> grid, const int* slots) {
   constexpr int NP = N + 1;
   extern __shared__ unsigned char smem_raw[];
-  cpx<T>* pl = reinterpret_cast<cpx<T>*>(smem_raw);
+  PlaneLds<N, T> L(smem_raw);
   const int slot = slots[blockIdx.y];
   const int i0 = blockIdx.x;
   const cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
-  plane_scatter<N, T>(pl, g, row);
-  plane_inverse<N, T>(pl, g, twiddles<T>(g));
+  plane_stage<N, T>(L, g);
+  plane_scatter<N, T>(L, g, row);
+  plane_inverse<N, P, T>(L, g);
   cpx<T>* dst = grid.base + slot * grid.stride + (long long)i0 * N * N;
   for (int e = threadIdx.x; e < N * N; e += PTHR) {
     const int i1 = e / N, i2 = e - (e / N) * N;
-    dst[e] = pl[i1 * NP + i2];
+    dst[e] = L.pl[i1 * NP + i2];
   }
 }
 
 // Delta n for perturbation j = blockIdx.y on plane i0 = blockIdx.x, summed over the
 // bands in a fixed order (deterministic, no atomics).
-template <int N>
+template <int N, int P>
 __global__ __launch_bounds__(PTHR) void k_drho(GridDev g, const z64* sticks, long long sstride,
                                                 int nband, const int* bands, const z64* psir,
                                                 double coef, double* drho) {
   constexpr int NP = N + 1;
   constexpr int PER = (N * N + PTHR - 1) / PTHR;
   extern __shared__ unsigned char smem_raw[];
-  z64* pl = reinterpret_cast<z64*>(smem_raw);
+  PlaneLds<N, double> L(smem_raw);
   const int j = blockIdx.y, i0 = blockIdx.x;
   const long long n3 = (long long)N * N * N;
+  plane_stage<N, double>(L, g);
   double acc[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) acc[q] = 0.0;
   for (int v = 0; v < nband; ++v) {
     const z64* row = sticks + ((long long)j * nband + v) * sstride + (long long)i0 * g.nst;
-    plane_scatter<N, double>(pl, g, row);
-    plane_inverse<N, double>(pl, g, g.tw64);
+    plane_scatter<N, double>(L, g, row);
+    plane_inverse<N, P, double>(L, g);
     const z64* pr = psir + (long long)bands[v] * n3 + (long long)i0 * N * N;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * PTHR;
       if (e < N * N) {
         const int i1 = e / N, i2 = e - (e / N) * N;
-        const z64 a = pr[e], d = pl[i1 * NP + i2];
+        const z64 a = pr[e], d = L.pl[i1 * NP + i2];
         acc[q] += a.x * d.x + a.y * d.y;
       }
     }
@@ -239,7 +279,7 @@ __global__ __launch_bounds__(PTHR) void k_drho(GridDev g, const z64* sticks, lon
 }
 
 template <int N, typename T>
-constexpr size_t plane_smem() { return size_t(N) * (N + 1) * sizeof(cpx<T>); }
+constexpr size_t plane_smem() { return PlaneLds<N, T>::bytes(); }
 
 // Raises the dynamic LDS limit of one kernel instantiation once per process.
 template <auto K>
@@ -252,26 +292,39 @@ void set_smem(size_t bytes) {
   }
 }
 
+template <typename T>
+int plan_of(const GridDev& g) { return g.plan[sizeof(T) == 4 ? 1 : 0]; }
+
 }  // namespace
 
-#define STH_DISPATCH_N(Nval, ...)                                                   \
-  switch (Nval) {                                                                   \
-    case 24: { constexpr int NN = 24; __VA_ARGS__; } break;                        \
-    case 48: { constexpr int NN = 48; __VA_ARGS__; } break;                        \
-    case 72: { constexpr int NN = 72; __VA_ARGS__; } break;                        \
-    case 96: { constexpr int NN = 96; __VA_ARGS__; } break;                        \
-    default: set_error("unsupported FFT grid %d (supported: 24, 48, 72, 96)", Nval); \
-             throw Error(STH_E_INVALID);                                            \
-  }
+// Compile-time dispatch over (grid length, radix plan).
+#define STH_DISPATCH_NP(Nval, Pval, ...)                                              \
+  do {                                                                                \
+    const int _p = (Pval);                                                            \
+    switch (Nval * 4 + _p) {                                                          \
+      case 24 * 4 + 0: { constexpr int NN = 24, PP = 0; __VA_ARGS__; } break;        \
+      case 24 * 4 + 1: { constexpr int NN = 24, PP = 1; __VA_ARGS__; } break;        \
+      case 48 * 4 + 0: { constexpr int NN = 48, PP = 0; __VA_ARGS__; } break;        \
+      case 48 * 4 + 1: { constexpr int NN = 48, PP = 1; __VA_ARGS__; } break;        \
+      case 72 * 4 + 0: { constexpr int NN = 72, PP = 0; __VA_ARGS__; } break;        \
+      case 72 * 4 + 1: { constexpr int NN = 72, PP = 1; __VA_ARGS__; } break;        \
+      case 96 * 4 + 0: { constexpr int NN = 96, PP = 0; __VA_ARGS__; } break;        \
+      case 96 * 4 + 1: { constexpr int NN = 96, PP = 1; __VA_ARGS__; } break;        \
+      default:                                                                        \
+        set_error("unsupported FFT grid %d / plan %d (grids 24, 48, 72, 96)", Nval, _p); \
+        throw Error(STH_E_INVALID);                                                   \
+    }                                                                                 \
+  } while (0)
 
 template <typename T, typename Tin>
 void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
                      const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
-  STH_DISPATCH_N(g.N, {
+  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     constexpr int ZS = zsticks<NN, T>();
     dim3 grid((g.nst + ZS - 1) / ZS, ncols);
-    hipLaunchKernelGGL((k_zfft_inv<NN, T, Tin>), grid, dim3(ZTHR), 0, st, g, in, sticks, slots);
+    hipLaunchKernelGGL((k_zfft_inv<NN, PP, T, Tin>), grid, dim3(ZTHR), 0, st, g, in, sticks,
+                       slots);
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -281,11 +334,11 @@ void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slot
                         const T* pot, const T* const* pot_ptr, hipStream_t st) {
   if (ncols <= 0) return;
   dim3 grid(g.N, ncols);
-  STH_DISPATCH_N(g.N, {
+  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     constexpr size_t sm = plane_smem<NN, T>();
-    set_smem<k_plane_local<NN, T>>(sm);
-    hipLaunchKernelGGL((k_plane_local<NN, T>), grid, dim3(PTHR), sm, st, g, sticks, slots, pot,
-                       pot_ptr);
+    set_smem<k_plane_local<NN, PP, T>>(sm);
+    hipLaunchKernelGGL((k_plane_local<NN, PP, T>), grid, dim3(PTHR), sm, st, g, sticks, slots,
+                       pot, pot_ptr);
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -295,11 +348,11 @@ void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout>
                      const int* slots, int ncols, int mode, VecSet<const Tout> pin,
                      const double* eps_slot, hipStream_t st) {
   if (ncols <= 0) return;
-  STH_DISPATCH_N(g.N, {
+  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     constexpr int ZS = zsticks<NN, T>();
     dim3 grid((g.nst + ZS - 1) / ZS, ncols);
-    hipLaunchKernelGGL((k_zfft_fwd<NN, T, Tout>), grid, dim3(ZTHR), 0, st, g, sticks, out, slots,
-                       mode, pin, eps_slot);
+    hipLaunchKernelGGL((k_zfft_fwd<NN, PP, T, Tout>), grid, dim3(ZTHR), 0, st, g, sticks, out,
+                       slots, mode, pin, eps_slot);
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -309,11 +362,11 @@ void launch_plane_to_grid(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<
                           const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
   dim3 grid(g.N, ncols);
-  STH_DISPATCH_N(g.N, {
+  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     constexpr size_t sm = plane_smem<NN, T>();
-    set_smem<k_plane_to_grid<NN, T>>(sm);
-    hipLaunchKernelGGL((k_plane_to_grid<NN, T>), grid, dim3(PTHR), sm, st, g, sticks, grid_out,
-                       slots);
+    set_smem<k_plane_to_grid<NN, PP, T>>(sm);
+    hipLaunchKernelGGL((k_plane_to_grid<NN, PP, T>), grid, dim3(PTHR), sm, st, g, sticks,
+                       grid_out, slots);
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -323,20 +376,31 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
                  hipStream_t st) {
   if (npert <= 0) return;
   dim3 grid(g.N, npert);
-  STH_DISPATCH_N(g.N, {
+  STH_DISPATCH_NP(g.N, plan_of<double>(g), {
     constexpr size_t sm = plane_smem<NN, double>();
-    set_smem<k_drho<NN>>(sm);
-    hipLaunchKernelGGL((k_drho<NN>), grid, dim3(PTHR), sm, st, g, sticks, stick_stride, nband,
-                       bands, psir, coef, drho);
+    set_smem<k_drho<NN, PP>>(sm);
+    hipLaunchKernelGGL((k_drho<NN, PP>), grid, dim3(PTHR), sm, st, g, sticks, stick_stride,
+                       nband, bands, psir, coef, drho);
   });
   STH_HIP_CHECK(hipGetLastError());
+}
+
+// Sets the LDS limits of every plane kernel of grid N up front, so that no
+// attribute call happens while a stream is being captured into a graph.
+void prepare_fft_kernels(int N) {
+  for (int p = 0; p < kRadixPlans; ++p) {
+    STH_DISPATCH_NP(N, p, {
+      set_smem<k_plane_local<NN, PP, double>>(plane_smem<NN, double>());
+      set_smem<k_plane_local<NN, PP, float>>(plane_smem<NN, float>());
+      set_smem<k_plane_to_grid<NN, PP, double>>(plane_smem<NN, double>());
+      set_smem<k_drho<NN, PP>>(plane_smem<NN, double>());
+    });
+  }
 }
 
 template void launch_zfft_inv<double, z64>(const GridDev&, VecSet<const z64>, VecSet<z64>,
                                            const int*, int, hipStream_t);
 template void launch_zfft_inv<float, z64>(const GridDev&, VecSet<const z64>, VecSet<z32>,
-                                          const int*, int, hipStream_t);
-template void launch_zfft_inv<float, z32>(const GridDev&, VecSet<const z32>, VecSet<z32>,
                                           const int*, int, hipStream_t);
 template void launch_plane_local<double>(const GridDev&, VecSet<z64>, const int*, int,
                                          const double*, const double* const*, hipStream_t);
@@ -347,9 +411,6 @@ template void launch_zfft_fwd<double, z64>(const GridDev&, VecSet<const z64>, Ve
                                            const double*, hipStream_t);
 template void launch_zfft_fwd<float, z64>(const GridDev&, VecSet<const z32>, VecSet<z64>,
                                           const int*, int, int, VecSet<const z64>,
-                                          const double*, hipStream_t);
-template void launch_zfft_fwd<float, z32>(const GridDev&, VecSet<const z32>, VecSet<z32>,
-                                          const int*, int, int, VecSet<const z32>,
                                           const double*, hipStream_t);
 template void launch_plane_to_grid<double>(const GridDev&, VecSet<const z64>, VecSet<z64>,
                                            const int*, int, hipStream_t);

@@ -13,7 +13,9 @@
 //
 // MFMA 16x16x4 lane layout (64 lanes, l = lane), measured on gfx950:
 //   A[i][k]: i = l % 16, k = l / 16;  B[k][j]: k = l / 16, j = l % 16;
-//   D[i][j], register v: i = l / 16 + 4 v, j = l % 16.
+//   D[i][j], register v: j = l % 16 and
+//     i = l / 16 + 4 v      for v_mfma_f64_16x16x4f64,
+//     i = 4 (l / 16) + v    for v_mfma_f32_16x16x4f32.
 #include "errors.hpp"
 #include "kernels.hpp"
 
@@ -29,6 +31,8 @@ struct Mfma<double> {
   __device__ static v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // output row of lane group kq = l / 16, register v
+  __device__ static int row(int kq, int v) { return kq + 4 * v; }
 };
 template <>
 struct Mfma<float> {
@@ -36,6 +40,7 @@ struct Mfma<float> {
   __device__ static v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static int row(int kq, int v) { return 4 * kq + v; }
 };
 
 constexpr int GT = 64;      // tile rows and columns
@@ -69,15 +74,27 @@ __global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const cpx<T>* __restrict__ A
     brow[i] = (n < ncols) ? B.base + (long long)slots[n] * B.stride : nullptr;
   }
   const int kq = lane >> 4, r16 = lane & 15;
-  for (int kb = kbeg; kb < kend; kb += GK) {
+  // the next K-tile is fetched into registers while the current one is multiplied
+  cpx<T> ra[4], rb[4];
+  auto fetch = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK, k = kb + c;
       const int m = m0 + row;
-      As[row][c] = (m < M && k < kend) ? A[(long long)m * lda + k] : cpx<T>{0, 0};
-      Bs[row][c] = (brow[i] && k < kend) ? rnd<T>(brow[i][k]) : cpx<T>{0, 0};
+      ra[i] = (m < M && k < kend) ? A[(long long)m * lda + k] : cpx<T>{0, 0};
+      rb[i] = (brow[i] && k < kend) ? rnd<T>(brow[i][k]) : cpx<T>{0, 0};
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int kb = kbeg; kb < kend; kb += GK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK;
+      As[row][c] = ra[i];
+      Bs[row][c] = rb[i];
     }
     __syncthreads();
+    if (kb + GK < kend) fetch(kb + GK);
 #pragma unroll
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int c = 2 * kk + (kq >> 1);
@@ -107,7 +124,7 @@ __global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const cpx<T>* __restrict__ A
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 32 + x * 16 + kq + 4 * v;
+        const int m = m0 + wm * 32 + x * 16 + Mfma<T>::row(kq, v);
         const int n = n0 + wn * 32 + y * 16 + r16;
         if (m < M && n < ncols)
           part[((long long)s * ncols + n) * M + m] = cpx<T>{accr[x][y][v], acci[x][y][v]};
@@ -153,22 +170,34 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const cpx<T>* __restrict__ A,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
-  for (int mb = 0; mb < M; mb += GK) {
+  // the next M-tile of W and C is fetched into registers during the multiply
+  cpx<T> rw[4], rc[4];
+  auto fetch = [&](int mb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR;
       {
         const int mr = idx / GT, gc = idx % GT;
         const int m = mb + mr, gg = g0 + gc;
-        Ws[mr][gc] = (m < M && gg < K) ? A[(long long)m * lda + gg] : cpx<T>{0, 0};
+        rw[i] = (m < M && gg < K) ? A[(long long)m * lda + gg] : cpx<T>{0, 0};
       }
       {
         const int nr = idx / GK, mc = idx % GK;
         const int n = n0 + nr, m = mb + mc;
-        Cs[nr][mc] = (n < ncols && m < M) ? C[(long long)n * M + m] : cpx<T>{0, 0};
+        rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : cpx<T>{0, 0};
       }
     }
+  };
+  if (M > 0) fetch(0);
+  for (int mb = 0; mb < M; mb += GK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + i * GTHR;
+      Ws[idx / GT][idx % GT] = rw[i];
+      Cs[idx / GK][idx % GK] = rc[i];
+    }
     __syncthreads();
+    if (mb + GK < M) fetch(mb + GK);
 #pragma unroll
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int mm = 2 * kk + (kq >> 1);
@@ -203,7 +232,7 @@ __global__ __launch_bounds__(GTHR) void k_gemm_a_c(const cpx<T>* __restrict__ A,
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gg = g0 + wg * 32 + x * 16 + kq + 4 * v;
+        const int gg = g0 + wg * 32 + x * 16 + Mfma<T>::row(kq, v);
         if (gg < K) {
           z64 o = {double(accr[x][y][v]), double(acci[x][y][v])};
           if (s0 != 0.0) {   // s0 == 0 never reads Y (it may be uninitialised)

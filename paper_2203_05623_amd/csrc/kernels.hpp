@@ -20,6 +20,7 @@ struct GridDev {
   const double* kin = nullptr;     // [npw] |G|^2 / 2
   const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
   const z32* tw32 = nullptr;       // [N] same, rounded to FP32
+  int plan[2] = {0, 0};            // radix plan of the FFT kernels: [0] FP64, [1] FP32
 };
 
 // A set of vectors addressed through a slot list: vector for list entry c is
@@ -55,6 +56,10 @@ void launch_plane_to_grid(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<
 void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, int nband,
                  const int* bands, const z64* psir, int npert, double coef, double* drho,
                  hipStream_t st);
+
+// LDS attributes of the plane kernels of grid N (call before any graph capture)
+void prepare_fft_kernels(int N);
+constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
 
 // ---- dense contractions on MFMA (FP64) ----
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)

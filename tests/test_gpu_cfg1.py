@@ -173,3 +173,38 @@ def test_invalid_arguments_are_errors(sth, cfg1, sys1):
     with pytest.raises(P.SthError) as e:
         P.sth_poll(ctx, t)
     assert e.value.code == P._lib.STH_E_NOT_FOUND
+
+
+def test_graph_replay_matches_direct_launches(cfg1):
+    """With fewer slots than solves the server reaches the steady state where the
+    captured hipGraph of CG iterations is replayed (with the server's own eager
+    refills, retirements and synchronisations between replays).  The result must
+    equal, bit for bit, a run with direct launches (deterministic reductions)."""
+    import os
+    import paper_2203_05623_amd as P
+    cfg, s, H, eps, Psi = cfg1
+    dv = workloads.dv_block(cfg, range(cfg.npert))
+    out = {}
+    for mode in ("1", "0"):
+        os.environ["STH_GRAPHS"] = mode
+        ctx = P.sth_create(device=0, max_slots=64)
+        try:
+            sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, Psi, eps)
+            for prec in (P.STH_FP64, P.STH_MIXED):
+                t = P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-10, precision=prec,
+                                        want_dpsi=True)
+                assert P.sth_wait(ctx, t, 120.0)
+                info = P.sth_poll(ctx, t)
+                x = np.empty((cfg.npert, NV, s.npw), np.complex128)
+                P.sth_fetch_dpsi(ctx, t, x)
+                out[(mode, prec)] = (x, info["graph_replays"])
+                P.sth_release_ticket(ctx, t)
+        finally:
+            P.sth_destroy(ctx)
+            os.environ.pop("STH_GRAPHS", None)
+    for prec in (P.STH_FP64, P.STH_MIXED):
+        xg, ng = out[("1", prec)]
+        xd, nd = out[("0", prec)]
+        print("precision", prec, "graph replays", ng, "direct", nd)
+        assert ng > 0 and nd == 0
+        assert np.array_equal(xg, xd)

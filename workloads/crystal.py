@@ -94,7 +94,7 @@ CONFIGS = {
     "cfg3": Config("cfg3", "diamond", 1, A_SI, 24, 26, 1, 8, 16, seed_kb=0, tol=1e-8,
                    precision="mixed"),
     # served systems of uneven size
-    "cfg4a": Config("cfg4a", "sc", 3, 13.68, 48, 132, 4, 54, 32, seed_kb=0, tol=1e-8,
+    "cfg4a": Config("cfg4a", "sc", 3, 13.68, 48, 132, 4, 54, 32, seed_kb=1, tol=1e-8,
                     precision="mixed"),
     "cfg4b": Config("cfg4b", "diamond", 2, 2 * A_SI, 72, 306, 4, 128, 32, seed_kb=9, tol=1e-8,
                     precision="mixed"),
