@@ -147,9 +147,16 @@ __host__ __device__ inline void stockham_load(const cpx<T>* buf, int base, int e
   for (int r = 0; r < R; ++r) v[r] = buf[base + (j + r * M) * es];
 }
 
-template <typename T, int N, int R, int NS, int SIGN>
+// Output hook of the last pass: identity (store the transform as is).
+struct NoPost {
+  template <typename C>
+  __host__ __device__ C operator()(int, C v) const { return v; }
+};
+
+template <typename T, int N, int R, int NS, int SIGN, typename Post = NoPost>
 __host__ __device__ inline void stockham_compute_store(cpx<T>* buf, int base, int es, int j,
-                                                       cpx<T>* v, const cpx<T>* tw) {
+                                                       cpx<T>* v, const cpx<T>* tw,
+                                                       Post post = Post()) {
   constexpr int STEP = N / (NS * R);
   const int k = j % NS;
   if (NS > 1) {
@@ -163,14 +170,19 @@ __host__ __device__ inline void stockham_compute_store(cpx<T>* buf, int base, in
   Dft<R, SIGN, T>::run(v);
   const int d = (j / NS) * NS * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) buf[base + (d + r * NS) * es] = v[r];
+  for (int r = 0; r < R; ++r) {
+    const int a = base + (d + r * NS) * es;
+    buf[a] = post(a, v[r]);
+  }
 }
 
 // One in-place pass over nfft transforms by the whole workgroup (NTHR threads).
 // All butterflies are loaded to registers before the barrier and stored after
 // it, so the pass can work in place.
-template <typename T, int N, int R, int NS, int SIGN, int NTHR, int NFFTMAX, typename BaseFn>
-__device__ inline void lds_pass(cpx<T>* buf, int nfft, int es, BaseFn base_of, const cpx<T>* tw) {
+template <typename T, int N, int R, int NS, int SIGN, int NTHR, int NFFTMAX, typename BaseFn,
+          typename Post = NoPost>
+__device__ inline void lds_pass(cpx<T>* buf, int nfft, int es, BaseFn base_of, const cpx<T>* tw,
+                                Post post = Post()) {
   constexpr int M = N / R;
   constexpr int MAXT = (NFFTMAX * M + NTHR - 1) / NTHR;
   const int ntask = nfft * M;
@@ -189,32 +201,49 @@ __device__ inline void lds_pass(cpx<T>* buf, int nfft, int es, BaseFn base_of, c
     const int t = threadIdx.x + q * NTHR;
     if (t < ntask) {
       const int f = t / M, j = t - f * M;
-      stockham_compute_store<T, N, R, NS, SIGN>(buf, base_of(f), es, j, v[q], tw);
+      stockham_compute_store<T, N, R, NS, SIGN>(buf, base_of(f), es, j, v[q], tw, post);
     }
   }
   __syncthreads();
 }
 
-// A full length-N transform as a chain of passes with radices R0, RS...
+// A full length-N transform as a chain of passes with radices R0, RS...; `post`
+// maps every output value (with its LDS index) as the last pass stores it.
 template <typename T, int N, int SIGN, int NTHR, int NFFTMAX, int NS, int R0, int... RS>
 struct LdsFFT {
-  template <typename BaseFn>
-  __device__ static void run(cpx<T>* buf, int nfft, int es, BaseFn base_of, const cpx<T>* tw) {
-    lds_pass<T, N, R0, NS, SIGN, NTHR, NFFTMAX>(buf, nfft, es, base_of, tw);
-    if constexpr (sizeof...(RS) > 0)
-      LdsFFT<T, N, SIGN, NTHR, NFFTMAX, NS * R0, RS...>::run(buf, nfft, es, base_of, tw);
+  template <typename BaseFn, typename Post = NoPost>
+  __device__ static void run(cpx<T>* buf, int nfft, int es, BaseFn base_of, const cpx<T>* tw,
+                             Post post = Post()) {
+    if constexpr (sizeof...(RS) > 0) {
+      lds_pass<T, N, R0, NS, SIGN, NTHR, NFFTMAX>(buf, nfft, es, base_of, tw);
+      LdsFFT<T, N, SIGN, NTHR, NFFTMAX, NS * R0, RS...>::run(buf, nfft, es, base_of, tw, post);
+    } else {
+      lds_pass<T, N, R0, NS, SIGN, NTHR, NFFTMAX>(buf, nfft, es, base_of, tw, post);
+    }
   }
 };
+
+// Threads that make every pass of a radix plan a single round over nfft
+// transforms (one butterfly per thread), rounded to whole wavefronts, at most 1024.
+template <int N, int R0, int... RS>
+constexpr int pass_threads(int nfft) {
+  int rmin = R0;
+  ((rmin = RS < rmin ? RS : rmin), ...);
+  const int t = nfft * (N / rmin);
+  const int w = ((t + 63) / 64) * 64;
+  return w > 1024 ? 1024 : w;
+}
 
 // Radix plans per length (first radix applied first); two plans per length,
 // chosen per system and precision by the autotuner (plan 0 is the default).
 template <int N, int P>
 struct RadixPlan;
-#define STH_RADIX_PLAN(NV, PV, ...)                                  \
-  template <>                                                        \
-  struct RadixPlan<NV, PV> {                                         \
-    template <typename T, int SIGN, int NTHR, int NFFTMAX>           \
-    using fft = LdsFFT<T, NV, SIGN, NTHR, NFFTMAX, 1, __VA_ARGS__>;  \
+#define STH_RADIX_PLAN(NV, PV, ...)                                             \
+  template <>                                                                   \
+  struct RadixPlan<NV, PV> {                                                    \
+    template <typename T, int SIGN, int NTHR, int NFFTMAX>                      \
+    using fft = LdsFFT<T, NV, SIGN, NTHR, NFFTMAX, 1, __VA_ARGS__>;             \
+    static constexpr int threads(int nfft) { return pass_threads<NV, __VA_ARGS__>(nfft); } \
   };
 STH_RADIX_PLAN(24, 0, 8, 3)
 STH_RADIX_PLAN(24, 1, 4, 6)
