@@ -29,7 +29,12 @@ import workloads  # noqa: E402
 
 METRIC = "Sternheimer solves/s, FP64 vs mixed at 1e-8 residual; p50/p99 solve latency"
 MI355X_HBM_GBS = 8000.0
-MI355X_FP64_TFLOPS = 78.6
+MI355X_FP64_TFLOPS = 78.6     # FP64 vector ALU and FP64 dense MFMA
+MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
+# (phase, precision) -> measured HBM bytes / algorithmic bytes of its kernel
+# (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
+# whenever the kernel changes
+HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0048}
 
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
@@ -230,6 +235,10 @@ def main():
     gap = float(eps[cfg.nv] - eps[cfg.nv - 1])
     sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
                            eps[:cfg.nv])
+    tinfo = P.sth_system_info_get(ctx, sid)
+    tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "fft_plan_fp32",
+                                    "plane_kernel_fp32", "gemm_kchunk", "tuned_from_cache")}
+    tuning["tune_ms"] = [round(x, 4) for x in tinfo["tune_ms"][:15]]
     prec = P.STH_FP64 if args.precision == "fp64" else P.STH_MIXED
     bands = np.arange(cfg.nv)
     dv = torch.from_numpy(dv).to("cuda:0")      # inputs resident in HBM before timing
@@ -267,19 +276,30 @@ def main():
     lat = np.concatenate(lats) * 1e3
     its = np.concatenate(iters)
     value = args.steps * nsolves / dt
-    # dominant kernel phase and its roofline
+    # dominant kernel phase and its roofline: the projector GEMMs against the
+    # MFMA peak, the plane stage (FFT butterflies on the vector ALUs) against the
+    # vector ALU peak with the nominal 5 N log2 N flops per transform, the other
+    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed
     dom = max(prof, key=lambda k: prof[k][0])
     ms, nl, by, fl = prof[dom]
-    if fl > 0:
-        roof = {"bound": "mfma", "achieved": fl / (ms * 1e-3) / 1e12, "peak": MI355X_FP64_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
+    kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
+    if kind == "hbm":
         roof = {"bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9, "peak": MI355X_HBM_GBS,
                 "unit": "GB/s"}
+    else:
+        peak = MI355X_FP64_TFLOPS if args.precision == "fp64" else MI355X_FP32_TFLOPS
+        roof = {"bound": kind, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (calibrated
+    # on a 1 GiB copy) as a multiple of the algorithmic bytes, where measured
+    ratio = HBM_OVER_ALGORITHMIC.get((dom, args.precision))
+    roof["traffic"] = None if ratio is None else ratio * by / max(nl, 1)
+    roof["traffic_unit"] = "bytes/launch"
     roof["kernel"] = dom
     roof["avg_launch_us"] = ms * 1e3 / max(nl, 1)
+    roof["algorithmic_bytes_per_launch"] = by / max(nl, 1)
+    roof["algorithmic_flops_per_launch"] = fl / max(nl, 1)
     phases = {k: {"ms": round(v[0], 3), "launches": v[1],
                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
                   "TFLOP/s": round(v[3] / (v[0] * 1e-3) / 1e12, 2) if v[0] > 0 and v[3] else None}
@@ -300,7 +320,7 @@ def main():
         "not_converged": bad, "max_true_rel_residual": worst,
         "setup": {"valence_s": t_val, "valence_iters": vits, "valence_residual": vres,
                   "gap_Ha": gap},
-        "roofline": roof, "phases": phases, "cpu_baseline": cpu,
+        "roofline": roof, "phases": phases, "tuning": tuning, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

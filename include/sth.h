@@ -137,16 +137,20 @@ sth_status sth_set_system(sth_ctx* ctx, const sth_system_desc* desc, void* strea
 
 /* Shape and tuning of a resident system.  The autotuner times, once per system
  * (or reads from the JSON-lines cache named by the environment variable
- * STH_TUNE_CACHE), each radix plan of the FFT kernels in FP64 and FP32 and the
- * split-K chunk of the projector GEMM on the system's real slot batch, and keeps
- * the fastest. */
+ * STH_TUNE_CACHE), each pair (radix plan, plane kernel variant) of the FFT
+ * stages in FP64 and FP32 and the split-K chunk of the projector GEMM on the
+ * system's real slot batch, and keeps the fastest. */
 typedef struct {
   int npw, nsticks, nslots, nv, nproj;
   int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
   int gemm_kchunk;                    /* split-K chunk of C = W^H P */
-  double tune_ms[8];                  /* timings behind the choice (plan0/1 fp64, plan0/1
-                                         fp32, kchunk candidates 0..2), ms per launch set */
+  double tune_ms[16];                 /* timings behind the choice, ms per launch set:
+                                         [6 p + 2 kind + plan] for precision p (0 FP64,
+                                         1 FP32), [12 + i] kchunk candidate i < 3 */
   int tuned_from_cache;
+  int plane_kernel_fp64, plane_kernel_fp32;   /* plane kernel variant: 0 single-pass
+                                                 workgroup per plane, 1 and 2 split
+                                                 i1 stage (two / three workgroups per CU) */
 } sth_system_info;
 sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 

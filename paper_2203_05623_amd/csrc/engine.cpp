@@ -335,6 +335,11 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.d_elem_pos = upload(&budget_, sb.elem_pos, st_);
   s.d_stick_i12 = upload(&budget_, sb.stick_i12, st_);
   s.d_row_list = upload(&budget_, sb.row_list, st_);
+  {
+    std::vector<int> idx12((size_t)N * N, -1);
+    for (int k = 0; k < s.nst; ++k) idx12[sb.stick_i12[k]] = k;
+    s.d_idx12 = upload(&budget_, idx12, st_);
+  }
   s.d_kin = upload(&budget_, sb.kin, st_);
   s.d_perm = upload(&budget_, sb.perm, st_);
   std::vector<z64> tw64(N);
@@ -354,6 +359,8 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.g.elem_pos = s.d_elem_pos.as<int>();
   s.g.stick_i12 = s.d_stick_i12.as<int>();
   s.g.row_list = s.d_row_list.as<int>();
+  s.g.idx12 = s.d_idx12.as<int>();
+  for (int r : sb.row_list) s.g.rowmask[r >> 6] |= 1ull << (r & 63);
   s.g.kin = s.d_kin.as<double>();
   s.g.tw64 = s.d_tw64.as<z64>();
   s.g.tw32 = s.d_tw32.as<z32>();
@@ -540,6 +547,16 @@ void Context::release_system(int id) {
 }
 
 // ------------------------------------------------------------------ operator
+// Nominal arithmetic of the plane stage for n vectors: per plane, inverse and
+// forward length-N transforms along i2 on the active rows and along i1 on all
+// columns, 5 N log2 N flops each (the usual FFT count), and the real potential
+// multiply (2 flops per point).
+static double plane_flops(const System& s, int n) {
+  const double N = s.N;
+  const double per_fft = 5.0 * N * std::log2(N);
+  return double(n) * N * ((2.0 * s.nrow + 2.0 * N) * per_fft + 2.0 * N * N);
+}
+
 // out = (H - eps_slot) in + W diag W^H in, on the listed vectors (slot pool
 // scratch: sticks, part, C).  With `dots`, partial Re<in, out> per 64-row tile.
 void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
@@ -557,7 +574,7 @@ void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const i
   prof_end(h, n * (vb + sb), 0.0);
   h = prof_begin(PH_PLANE);
   launch_plane_local<double>(s.g, sticks, dl, n, s.d_vloc.as<double>(), nullptr, st_);
-  prof_end(h, n * 2.0 * sb + double(N) * N * N * 8.0, 0.0);
+  prof_end(h, n * 2.0 * sb + double(N) * N * N * 8.0, plane_flops(s, n));
   h = prof_begin(PH_ZFWD);
   launch_zfft_fwd<double, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
                                s.ss.eps, st_);
@@ -592,7 +609,7 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   prof_end(h, n * (vb + sb), 0.0);
   h = prof_begin(PH_PLANE);
   launch_plane_local<float>(s.g, sticks, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
-  prof_end(h, n * 2.0 * sb + double(N) * N * N * 4.0, 0.0);
+  prof_end(h, n * 2.0 * sb + double(N) * N * N * 4.0, plane_flops(s, n));
   h = prof_begin(PH_ZFWD);
   launch_zfft_fwd<float, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
                               s.ss.eps, st_);

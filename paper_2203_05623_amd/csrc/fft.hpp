@@ -88,11 +88,13 @@ struct Dft<8, SIGN, T> {
 };
 
 // Composite codelet R = P * Q:  n = P n1 + n2 (n1 < Q, n2 < P), k = k1 + Q k2.
-// Inner DFTs of length Q over n1, twiddle w_R^(n2 k1), outer DFTs of length P over n2.
+// Inner DFTs of length Q over n1, twiddle w_R^(n2 k1), outer DFTs of length P over
+// n2.  Both stages work in place on v (an inner DFT reads and writes the cells
+// P n1 + n2 of one n2, an outer DFT the cells P k1 + n2 of one k1), so at most
+// R + max(P, Q) values are live; the final reordering is a register renaming.
 template <int P, int Q, int SIGN, typename T>
 __host__ __device__ inline void dft_composite(cpx<T>* v) {
   constexpr int R = P * Q;
-  cpx<T> y[P][Q];
 #pragma unroll
   for (int n2 = 0; n2 < P; ++n2) {
     cpx<T> t[Q];
@@ -102,12 +104,12 @@ __host__ __device__ inline void dft_composite(cpx<T>* v) {
 #pragma unroll
     for (int k1 = 0; k1 < Q; ++k1) {
       if (n2 * k1 == 0) {
-        y[n2][k1] = t[k1];
+        v[P * k1 + n2] = t[k1];
       } else {
         // exp(SIGN 2 pi i n2 k1 / R), folded to constants by the compiler
         const double ang = 6.283185307179586476925 * double(n2 * k1) / double(R);
-        cpx<T> w = {T(__builtin_cos(ang)), T(SIGN * __builtin_sin(ang))};
-        y[n2][k1] = t[k1] * w;
+        const cpx<T> w = {T(__builtin_cos(ang)), T(SIGN * __builtin_sin(ang))};
+        v[P * k1 + n2] = t[k1] * w;
       }
     }
   }
@@ -115,11 +117,19 @@ __host__ __device__ inline void dft_composite(cpx<T>* v) {
   for (int k1 = 0; k1 < Q; ++k1) {
     cpx<T> t[P];
 #pragma unroll
-    for (int n2 = 0; n2 < P; ++n2) t[n2] = y[n2][k1];
+    for (int n2 = 0; n2 < P; ++n2) t[n2] = v[P * k1 + n2];
     Dft<P, SIGN, T>::run(t);
 #pragma unroll
-    for (int k2 = 0; k2 < P; ++k2) v[k1 + Q * k2] = t[k2];
+    for (int k2 = 0; k2 < P; ++k2) v[P * k1 + k2] = t[k2];
   }
+  // v[P k1 + k2] holds X[k1 + Q k2]
+  cpx<T> o[R];
+#pragma unroll
+  for (int k1 = 0; k1 < Q; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < P; ++k2) o[k1 + Q * k2] = v[P * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = o[i];
 }
 
 template <int SIGN, typename T>
@@ -244,6 +254,10 @@ struct RadixPlan;
     template <typename T, int SIGN, int NTHR, int NFFTMAX>                      \
     using fft = LdsFFT<T, NV, SIGN, NTHR, NFFTMAX, 1, __VA_ARGS__>;             \
     static constexpr int threads(int nfft) { return pass_threads<NV, __VA_ARGS__>(nfft); } \
+    static constexpr int radix(int i) {                                         \
+      constexpr int rs[] = {__VA_ARGS__};                                       \
+      return rs[i];                                                             \
+    }                                                                           \
   };
 STH_RADIX_PLAN(24, 0, 8, 3)
 STH_RADIX_PLAN(24, 1, 4, 6)
@@ -257,5 +271,25 @@ STH_RADIX_PLAN(144, 0, 16, 9)
 STH_RADIX_PLAN(144, 1, 9, 16)
 #undef STH_RADIX_PLAN
 constexpr int kRadixPlans = 2;
+
+// ------------------------------------------------------------------ two-pass plans
+// Every plan above has two radices, N = R1 R2.  The inverse transform is pass 1
+// (radix R1, N/R1 butterflies, no twiddles) then pass 2 (radix R2, N/R2 = R1
+// butterflies; butterfly j reads and writes the cells j + r R1 and multiplies
+// input r by exp(+2 pi i r j / N)).  The forward transform is used in the form
+// of the adjoint of that sequence: pass 2^H (DFT of sign -1 over the cells
+// j + q R1, then the conjugate twiddles, written back to the same cells) and
+// pass 1^H (reads the cells where pass 1 wrote, writes natural order).
+//
+// w[r] = exp(+2 pi i r j / N), r < R, from w1 = tw[j] = exp(-2 pi i j / N) by a
+// balanced product tree (each power is at most ceil(log2 R) products deep).
+template <int R, typename T>
+__host__ __device__ inline void twiddle_powers(cpx<T> w1, cpx<T>* w) {
+  w1.y = -w1.y;
+  w[0] = cpx<T>{T(1), T(0)};
+  if constexpr (R > 1) w[1] = w1;
+#pragma unroll
+  for (int r = 2; r < R; ++r) w[r] = w[r / 2] * w[r - r / 2];
+}
 
 }  // namespace sth

@@ -105,17 +105,23 @@ __global__ void k_cg_init_scalars(const double* part2, int nchunk, const int* sl
   s.status[slot] = (b > 0.0) ? SLOT_ACTIVE : (b == 0.0 ? SLOT_DONE : SLOT_NAN);
 }
 
-__global__ void k_cg_alpha(const double* dots, int ntile, const int* slots, int ncols,
-                           SlotState s) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// alpha = rho / <p, A p> per column: one wavefront per column sums the per-tile
+// partials (lane l takes tiles l, l + 64, ...; then a fixed butterfly order).
+__global__ __launch_bounds__(64) void k_cg_alpha(const double* dots, int ntile,
+                                                 const int* slots, int ncols, SlotState s) {
+  const int c = blockIdx.x;
   if (c >= ncols) return;
   const int slot = slots[c];
+  const int l = threadIdx.x;
+  double pq = 0.0;
+  for (int t = l; t < ntile; t += 64) pq += dots[(long long)c * ntile + t];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pq += __shfl_xor(pq, o);
+  if (l != 0) return;
   if (s.status[slot] != SLOT_ACTIVE) {
     s.alpha[slot] = 0.0;
     return;
   }
-  double pq = 0.0;
-  for (int t = 0; t < ntile; ++t) pq += dots[(long long)c * ntile + t];
   if (pq > 0.0) {
     s.alpha[slot] = s.rho[slot] / pq;
   } else {
@@ -380,8 +386,7 @@ void launch_cg_init_scalars(const double* part2, int nchunk, const int* slots, i
 void launch_cg_alpha(const double* dots, int ntile, const int* slots, int ncols, SlotState s,
                      hipStream_t st) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(k_cg_alpha, scalar_grid(ncols), dim3(128), 0, st, dots, ntile, slots, ncols,
-                     s);
+  hipLaunchKernelGGL(k_cg_alpha, dim3(ncols), dim3(64), 0, st, dots, ntile, slots, ncols, s);
   STH_HIP_CHECK(hipGetLastError());
 }
 

@@ -8,10 +8,11 @@
 //              and inverse-transformed.  Output layout [i0][stick] so that a
 //              plane (fixed i0) of all sticks is one contiguous row.
 //   plane_*    one workgroup per (vector, i0): the stick values of the plane
-//              are scattered into an N x N LDS tile, inverse-transformed along
+//              go into an N x (N + 1) LDS tile, are inverse-transformed along
 //              i2 (only rows that hold sticks) and i1, multiplied by the real
-//              potential (fused into the stores of the last inverse pass),
-//              transformed forward and gathered back.
+//              potential, transformed forward and written back to the sticks.
+//              k_plane_local does this with the forward transforms taken as
+//              the adjoints of the inverse pass sequence (see there).
 //   zfft_fwd   z-sticks -> sphere: forward transform along axis 0, 1/N^3, the
 //              sphere components extracted, kinetic and shift terms fused.
 // Every kernel is instantiated for each radix plan of its length; the plan used
@@ -44,7 +45,6 @@ constexpr int pthreads() {
   const int t = RadixPlan<N, P>::threads(N);
   return t < 256 ? 256 : t;
 }
-
 template <typename T>
 __device__ inline const cpx<T>* twiddles(const GridDev& g);
 template <>
@@ -211,48 +211,452 @@ __device__ inline void plane_scatter(PlaneLds<N, T>& L, const GridDev& g, const 
   __syncthreads();
 }
 
-template <int N, int P, typename T>
-__global__ __launch_bounds__((pthreads<N, P>())) void k_plane_local(GridDev g,
-                                                                   VecSet<cpx<T>> sticks,
-                                                                   const int* slots, const T* pot,
-                                                                   const T* const* pot_ptr) {
-  constexpr int NT = pthreads<N, P>();
+// w[r] = tw[r j] = exp(-2 pi i r j / N) for r < R.  FP64 reads every power from
+// the table (exact); FP32 reads w^1 and forms the other powers by a balanced
+// product tree (one load instead of R - 1, each power at most ceil(log2 R)
+// roundings deep).
+template <int R, typename T>
+__device__ inline void pass_twiddles(const cpx<T>* tw, int j, cpx<T>* w) {
+  w[0] = cpx<T>{T(1), T(0)};
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = tw[r * j];
+  } else {
+    if constexpr (R > 1) w[1] = tw[j];
+#pragma unroll
+    for (int r = 2; r < R; ++r) w[r] = w[r / 2] * w[r - r / 2];
+  }
+}
+
+// The stick row of plane i0 into the tile (coalesced reads; cells without a
+// stick keep stale values, the first pass reads them as zero), and back.
+template <int N, int NT, typename T>
+__device__ inline void sticks_to_tile(cpx<T>* tile, const GridDev& g, const cpx<T>* row) {
   constexpr int NP = N + 1;
+  for (int s = threadIdx.x; s < g.nst; s += NT) {
+    const int p = g.stick_i12[s];
+    const int i1 = p / N;
+    tile[i1 * NP + (p - i1 * N)] = row[s];
+  }
+}
+template <int N, int NT, typename T>
+__device__ inline void tile_to_sticks(const cpx<T>* tile, const GridDev& g, cpx<T>* row) {
+  constexpr int NP = N + 1;
+  for (int s = threadIdx.x; s < g.nst; s += NT) {
+    const int p = g.stick_i12[s];
+    const int i1 = p / N;
+    row[s] = tile[i1 * NP + (p - i1 * N)];
+  }
+}
+
+// Bit i1 of the active-row mask (rows holding at least one stick).
+__device__ inline bool row_active(const GridDev& g, int i1) {
+  const unsigned long long m =
+      i1 < 64 ? g.rowmask[0] : (i1 < 128 ? g.rowmask[1] : g.rowmask[2]);
+  return (m >> (i1 & 63)) & 1ull;
+}
+
+// H_loc on one plane, single-pass form: one workgroup per (vector, i0) holding
+// the whole N x (N + 1) tile.  The forward transforms are the adjoints of the
+// inverse pass sequence (N = R1 R2), so the inverse pass 2 along i1, the
+// potential multiply and the forward pass 2^H along i1 share one butterfly's
+// registers, and every pass 2 / 2^H works in place (no barrier between its
+// loads and stores):
+//   A1   along i2, pass 1 on the active rows; inputs gathered from the stick row
+//   A2   along i2, pass 2 on the active rows
+//   B1   along i1, pass 1 on all columns; inputs from the active rows only
+//   B2   along i1, pass 2, * V, pass 2^H
+//   B1h  along i1, pass 1^H; outputs kept for the active rows only
+//   A2h  along i2, pass 2^H on the active rows
+//   A1h  along i2, pass 1^H; outputs scattered straight to the stick row
+// Passes along i2 give consecutive lanes consecutive rows (odd LDS pitch), passes
+// along i1 consecutive columns: no bank conflicts either way.
+template <int N, int P>
+constexpr int fused_threads() {
+  return pthreads<N, P>();
+}
+template <int N, typename T>
+constexpr size_t fused_lds_bytes() {
+  return size_t(N) * (N + 1) * sizeof(cpx<T>);
+}
+
+template <int N, int P, typename T>
+__global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
+    GridDev g, VecSet<cpx<T>> sticks, const int* slots, const T* pot, const T* const* pot_ptr) {
+  constexpr int NT = fused_threads<N, P>();
+  constexpr int NP = N + 1;
+  constexpr int R1 = RadixPlan<N, P>::radix(0), R2 = RadixPlan<N, P>::radix(1);
+  static_assert(R1 * R2 == N, "two-pass plan");
+  constexpr int M1 = N / R1, M2 = N / R2;
+  constexpr int TB1 = (N * M1 + NT - 1) / NT;
+  constexpr int TB2 = (N * M2 + NT - 1) / NT;
   extern __shared__ unsigned char smem_raw[];
-  PlaneLds<N, T> L(smem_raw);
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem_raw);
   const int slot = slots[blockIdx.y];
   const int i0 = blockIdx.x;
   cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
   const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
-  plane_stage<N, NT, T>(L, g);
-  if constexpr (PlaneLds<N, T>::kStageV) {
-    for (int e = threadIdx.x; e < N * N; e += NT) L.v[e] = V[e];   // coalesced
-  }
-  plane_scatter<N, NT, T>(L, g, row);
-  if constexpr (PlaneLds<N, T>::kStageV) {
-    const T* lv = L.v;
-    plane_inverse<N, P, NT, T>(L, g, [lv](int a, cpx<T> c) {
-      const int i1 = a / NP, i2 = a - (a / NP) * NP;
-      const T s = lv[i1 * N + i2];
-      return cpx<T>{c.x * s, c.y * s};
-    });
-  } else {
-    plane_inverse<N, P, NT, T>(L, g);
-    for (int e = threadIdx.x; e < N * N; e += NT) {
-      const int i1 = e / N, i2 = e - (e / N) * N;
-      const T s = V[e];
-      cpx<T>& c = L.pl[i1 * NP + i2];
-      c.x *= s;
-      c.y *= s;
+  const cpx<T>* tw = twiddles<T>(g);
+  const int* idx = g.idx12;
+  const int nrow = g.nrow;
+
+  sticks_to_tile<N, NT, T>(tile, g, row);
+  __syncthreads();
+  {   // A1: loads, barrier, stores (in place along the row)
+    constexpr int TA = (N / 2 * M1 + NT - 1) / NT;   // at most N/2 active rows
+    cpx<T> v[TA][R1];
+#pragma unroll
+    for (int q = 0; q < TA; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nrow * M1) {
+        const int f = t / M1, j = t - f * M1;
+        const int i1 = g.row_list[f];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          v[q][r] = cpx<T>{T(0), T(0)};
+          if (idx[i1 * N + j + r * M1] >= 0) v[q][r] = tile[i1 * NP + j + r * M1];
+        }
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TA; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nrow * M1) {
+        const int f = t / M1, j = t - f * M1;
+        const int i1 = g.row_list[f];
+        Dft<R1, +1, T>::run(v[q]);
+#pragma unroll
+        for (int p = 0; p < R1; ++p) tile[i1 * NP + j * R1 + p] = v[q][p];
+      }
+    }
   }
-  plane_forward<N, P, NT, T>(L, g);
-  for (int s = threadIdx.x; s < g.nst; s += NT) {
-    const int p = g.stick_i12[s];
-    const int i1 = p / N, i2 = p - (p / N) * N;
-    row[s] = L.pl[i1 * NP + i2];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nrow * M2; t += NT) {   // A2
+    const int j = t / nrow, f = t - j * nrow;
+    const int i1 = g.row_list[f];
+    cpx<T> v[R2], w[R2];
+    pass_twiddles<R2>(tw, j, w);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[r] = tile[i1 * NP + j + r * M2];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) v[r] = v[r] * conj(w[r]);
+    Dft<R2, +1, T>::run(v);
+#pragma unroll
+    for (int q = 0; q < R2; ++q) tile[i1 * NP + j + q * M2] = v[q];
   }
+  __syncthreads();
+  {   // B1
+    cpx<T> v[TB1][R1];
+#pragma unroll
+    for (int q = 0; q < TB1; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < N * M1) {
+        const int j = t / N, c = t - j * N;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int i1 = j + r * M1;
+          v[q][r] = cpx<T>{T(0), T(0)};
+          if (row_active(g, i1)) v[q][r] = tile[i1 * NP + c];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TB1; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < N * M1) {
+        const int j = t / N, c = t - j * N;
+        Dft<R1, +1, T>::run(v[q]);
+#pragma unroll
+        for (int p = 0; p < R1; ++p) tile[(j * R1 + p) * NP + c] = v[q][p];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TB2; ++q) {   // B2
+    const int t = threadIdx.x + q * NT;
+    if (t < N * M2) {
+      const int j = t / N, c = t - j * N;
+      cpx<T> v[R2], w[R2];
+      pass_twiddles<R2>(tw, j, w);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = tile[(j + r * M2) * NP + c];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) v[r] = v[r] * conj(w[r]);
+      Dft<R2, +1, T>::run(v);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = scale(v[r], V[(j + r * M2) * N + c]);
+      Dft<R2, -1, T>::run(v);
+      tile[j * NP + c] = v[0];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) tile[(j + r * M2) * NP + c] = v[r] * w[r];
+    }
+  }
+  __syncthreads();
+  {   // B1h
+    cpx<T> v[TB1][R1];
+#pragma unroll
+    for (int q = 0; q < TB1; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < N * M1) {
+        const int j = t / N, c = t - j * N;
+#pragma unroll
+        for (int p = 0; p < R1; ++p) v[q][p] = tile[(j * R1 + p) * NP + c];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TB1; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < N * M1) {
+        const int j = t / N, c = t - j * N;
+        Dft<R1, -1, T>::run(v[q]);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int i1 = j + r * M1;
+          if (row_active(g, i1)) tile[i1 * NP + c] = v[q][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nrow * M2; t += NT) {   // A2h
+    const int j = t / nrow, f = t - j * nrow;
+    const int i1 = g.row_list[f];
+    cpx<T> v[R2], w[R2];
+    pass_twiddles<R2>(tw, j, w);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[r] = tile[i1 * NP + j + r * M2];
+    Dft<R2, -1, T>::run(v);
+#pragma unroll
+    for (int r = 1; r < R2; ++r) v[r] = v[r] * w[r];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) tile[i1 * NP + j + r * M2] = v[r];
+  }
+  __syncthreads();
+  {   // A1h: loads, barrier, stores; then the stick cells go back to the row
+    constexpr int TA = (N / 2 * M1 + NT - 1) / NT;
+    cpx<T> v[TA][R1];
+#pragma unroll
+    for (int q = 0; q < TA; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nrow * M1) {
+        const int f = t / M1, j = t - f * M1;
+        const int i1 = g.row_list[f];
+#pragma unroll
+        for (int p = 0; p < R1; ++p) v[q][p] = tile[i1 * NP + j * R1 + p];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TA; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < nrow * M1) {
+        const int f = t / M1, j = t - f * M1;
+        const int i1 = g.row_list[f];
+        Dft<R1, -1, T>::run(v[q]);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) tile[i1 * NP + j + r * M1] = v[q][r];
+      }
+    }
+  }
+  __syncthreads();
+  tile_to_sticks<N, NT, T>(tile, g, row);
+}
+
+// H_loc on one plane, wave form: the passes of k_plane_fused, with every
+// transform owned by one wavefront.  A wave takes PW rows (passes along i2) or
+// PW columns (passes along i1) and runs all passes of that direction on them;
+// the exchanges between those passes stay inside the wave, so they need only a
+// wave-level ordering point, and the workgroup meets at two barriers per plane
+// (after the i2 inverse passes, after the i1 passes).  Waves drift apart between
+// the barriers, so one wave's LDS waits overlap another's arithmetic.
+// Lane mapping: lane = j * PW + q (butterfly j, transform q of the wave's group),
+// so consecutive lanes take consecutive rows (LDS stride N + 1) or consecutive
+// columns (stride 1, and coalesced potential reads).  (Measured on gfx950: this
+// order beats butterfly-fastest lanes, whose cells are bank-disjoint on paper.)
+template <int N, int P>
+struct PlaneWave {
+  static constexpr int R1 = RadixPlan<N, P>::radix(0), R2 = RadixPlan<N, P>::radix(1);
+  static_assert(R1 * R2 == N, "two-pass plan");
+  static constexpr int M1 = N / R1;   // butterflies of pass 1 per transform (= R2)
+  static constexpr int M2 = N / R2;   // butterflies of pass 2 per transform (= R1)
+  static constexpr int MM = M1 > M2 ? M1 : M2;
+  static constexpr int PW = 64 / MM;                // transforms per wave
+  static constexpr int NG = (N + PW - 1) / PW;      // column groups of a plane
+  static constexpr int NW = NG < 12 ? NG : 12;      // waves per workgroup
+  static constexpr int NT = NW * 64;
+  static constexpr int NP = N + 1;
+  static constexpr size_t lds_bytes(size_t elem) { return size_t(N) * NP * elem; }
+  // register budget: one FP64 workgroup per CU (its tile takes half the LDS or
+  // more), two FP32 workgroups
+  template <typename T>
+  static constexpr int waves_per_eu() {
+    const int w = ((sizeof(T) == 4 && 2 * NW <= 24 ? 2 : 1) * NW + 3) / 4;
+    return w > 8 ? 8 : w;
+  }
+};
+
+// Orders the LDS accesses of one wavefront across lanes (a wave executes in
+// lockstep; this only stops the compiler from moving accesses across it).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, int P, typename T>
+__global__ __launch_bounds__((PlaneWave<N, P>::NT))
+__attribute__((amdgpu_waves_per_eu(PlaneWave<N, P>::template waves_per_eu<T>()))) void k_plane_wave(
+    GridDev g, VecSet<cpx<T>> sticks, const int* slots, const T* pot, const T* const* pot_ptr) {
+  using S = PlaneWave<N, P>;
+  constexpr int R1 = S::R1, R2 = S::R2, M1 = S::M1, M2 = S::M2, PW = S::PW, NW = S::NW;
+  constexpr int NP = S::NP;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int slot = slots[blockIdx.y];
+  const int i0 = blockIdx.x;
+  cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+  const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+  const cpx<T>* tw = twiddles<T>(g);
+  const int* idx = g.idx12;
+  const int nrow = g.nrow;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // lane = j * PW + q: butterfly j of transform q of the wave's group
+  const int j1 = lane / PW, q1 = lane - j1 * PW;
+  const int j2 = j1, q2 = q1;
+  // the passes that touch the stick row take lane = q * M1 + j instead, so that
+  // consecutive lanes read and write consecutive sticks of one row
+  const int qg = lane / M1, jg = lane - qg * M1;
+  const int nga = (nrow + PW - 1) / PW;
+
+  sticks_to_tile<N, S::NT, T>(tile, g, row);
+  __syncthreads();
+  // along i2, inverse: A1 then A2 on the wave's rows
+  for (int grp = wave; grp < nga; grp += NW) {
+    const int fg = grp * PW + qg, f2 = grp * PW + q2;
+    const bool a1 = qg < PW && fg < nrow;
+    const int ig = a1 ? g.row_list[fg] : 0;
+    cpx<T> v[R1];
+    if (a1) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        v[r] = cpx<T>{T(0), T(0)};
+        if (idx[ig * N + jg + r * M1] >= 0) v[r] = tile[ig * NP + jg + r * M1];
+      }
+    }
+    wave_sync();
+    if (a1) {
+      Dft<R1, +1, T>::run(v);
+#pragma unroll
+      for (int q = 0; q < R1; ++q) tile[ig * NP + jg * R1 + q] = v[q];
+    }
+    wave_sync();
+    if (j2 < M2 && f2 < nrow) {
+      const int i1 = g.row_list[f2];
+      cpx<T> v[R2], w[R2];
+      pass_twiddles<R2>(tw, j2, w);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = tile[i1 * NP + j2 + r * M2];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) v[r] = v[r] * conj(w[r]);
+      Dft<R2, +1, T>::run(v);
+#pragma unroll
+      for (int q = 0; q < R2; ++q) tile[i1 * NP + j2 + q * M2] = v[q];
+    }
+    wave_sync();
+  }
+  __syncthreads();
+
+  // along i1: pass 1, pass 2 * V * pass 2^H, pass 1^H on the wave's columns
+  for (int grp = wave; grp < S::NG; grp += NW) {
+    const int c1 = grp * PW + q1, c2 = grp * PW + q2;
+    const bool b1 = j1 < M1 && c1 < N;
+    const bool b2 = j2 < M2 && c2 < N;
+    cpx<T> v[R1];
+    if (b1) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int i1 = j1 + r * M1;
+        v[r] = cpx<T>{T(0), T(0)};
+        if (row_active(g, i1)) v[r] = tile[i1 * NP + c1];
+      }
+    }
+    wave_sync();
+    if (b1) {
+      Dft<R1, +1, T>::run(v);
+#pragma unroll
+      for (int p = 0; p < R1; ++p) tile[(j1 * R1 + p) * NP + c1] = v[p];
+    }
+    wave_sync();
+    if (b2) {
+      cpx<T> u[R2], w[R2];
+      pass_twiddles<R2>(tw, j2, w);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = tile[(j2 + r * M2) * NP + c2];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) u[r] = u[r] * conj(w[r]);
+      Dft<R2, +1, T>::run(u);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) u[r] = scale(u[r], V[(j2 + r * M2) * N + c2]);
+      Dft<R2, -1, T>::run(u);
+      tile[j2 * NP + c2] = u[0];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) tile[(j2 + r * M2) * NP + c2] = u[r] * w[r];
+    }
+    wave_sync();
+    if (b1) {
+#pragma unroll
+      for (int p = 0; p < R1; ++p) v[p] = tile[(j1 * R1 + p) * NP + c1];
+    }
+    wave_sync();
+    if (b1) {
+      Dft<R1, -1, T>::run(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int i1 = j1 + r * M1;
+        if (row_active(g, i1)) tile[i1 * NP + c1] = v[r];
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+
+  // along i2, forward: A2h then A1h on the wave's rows
+  for (int grp = wave; grp < nga; grp += NW) {
+    const int fg = grp * PW + qg, f2 = grp * PW + q2;
+    if (j2 < M2 && f2 < nrow) {
+      const int i1 = g.row_list[f2];
+      cpx<T> v[R2], w[R2];
+      pass_twiddles<R2>(tw, j2, w);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = tile[i1 * NP + j2 + r * M2];
+      Dft<R2, -1, T>::run(v);
+#pragma unroll
+      for (int r = 1; r < R2; ++r) v[r] = v[r] * w[r];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) tile[i1 * NP + j2 + r * M2] = v[r];
+    }
+    wave_sync();
+    const bool a1 = qg < PW && fg < nrow;
+    const int ig = a1 ? g.row_list[fg] : 0;
+    cpx<T> v[R1];
+    if (a1) {
+#pragma unroll
+      for (int p = 0; p < R1; ++p) v[p] = tile[ig * NP + jg * R1 + p];
+    }
+    wave_sync();
+    if (a1) {
+      Dft<R1, -1, T>::run(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) tile[ig * NP + jg + r * M1] = v[r];
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  tile_to_sticks<N, S::NT, T>(tile, g, row);
 }
 
 template <int N, int P, typename T>
@@ -365,16 +769,30 @@ void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> stic
   STH_HIP_CHECK(hipGetLastError());
 }
 
+// Plane kernel variants (GridDev::plane_kind): 0 single-pass workgroup form,
+// 1 wave form.
 template <typename T>
 void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
                         const T* pot, const T* const* pot_ptr, hipStream_t st) {
   if (ncols <= 0) return;
   dim3 grid(g.N, ncols);
+  const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
+  if (2 * g.nrow > g.N) {   // an alias-free sphere has at most N/2 rows
+    set_error("plane kernel: %d active rows exceed N/2 = %d", g.nrow, g.N / 2);
+    throw Error(STH_E_INVALID);
+  }
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
-    constexpr size_t sm = PlaneLds<NN, T>::bytes(true);
-    set_smem<k_plane_local<NN, PP, T>>(sm);
-    hipLaunchKernelGGL((k_plane_local<NN, PP, T>), grid, dim3(pthreads<NN, PP>()), sm, st, g,
-                       sticks, slots, pot, pot_ptr);
+    if (kind == 0) {
+      constexpr size_t sm = fused_lds_bytes<NN, T>();
+      constexpr int nt = fused_threads<NN, PP>();
+      hipLaunchKernelGGL((k_plane_fused<NN, PP, T>), grid, dim3(nt), sm, st, g, sticks, slots,
+                         pot, pot_ptr);
+    } else {
+      using S = PlaneWave<NN, PP>;
+      constexpr size_t sm = S::lds_bytes(sizeof(cpx<T>));
+      hipLaunchKernelGGL((k_plane_wave<NN, PP, T>), grid, dim3(S::NT), sm, st, g, sticks, slots,
+                         pot, pot_ptr);
+    }
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -426,8 +844,10 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 void prepare_fft_kernels(int N) {
   for (int p = 0; p < kRadixPlans; ++p) {
     STH_DISPATCH_NP(N, p, {
-      set_smem<k_plane_local<NN, PP, double>>(PlaneLds<NN, double>::bytes(true));
-      set_smem<k_plane_local<NN, PP, float>>(PlaneLds<NN, float>::bytes(true));
+      set_smem<k_plane_fused<NN, PP, double>>(fused_lds_bytes<NN, double>());
+      set_smem<k_plane_fused<NN, PP, float>>(fused_lds_bytes<NN, float>());
+      set_smem<k_plane_wave<NN, PP, double>>(PlaneWave<NN, PP>::lds_bytes(sizeof(z64)));
+      set_smem<k_plane_wave<NN, PP, float>>(PlaneWave<NN, PP>::lds_bytes(sizeof(z32)));
       set_smem<k_plane_to_grid<NN, PP, double>>(PlaneLds<NN, double>::bytes(false));
       set_smem<k_drho<NN, PP>>(PlaneLds<NN, double>::bytes(false));
     });

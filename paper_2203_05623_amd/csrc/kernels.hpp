@@ -17,10 +17,13 @@ struct GridDev {
   const int* elem_pos = nullptr;   // [npw] stick * N + i0 of each element
   const int* stick_i12 = nullptr;  // [nst] i1 * N + i2 of each stick
   const int* row_list = nullptr;   // [nrow] active i1 rows
+  const int* idx12 = nullptr;      // [N * N] stick at (i1, i2), -1 where there is none
+  unsigned long long rowmask[3] = {0, 0, 0};  // bit i1: row i1 is active (N <= 192)
   const double* kin = nullptr;     // [npw] |G|^2 / 2
   const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
   const z32* tw32 = nullptr;       // [N] same, rounded to FP32
   int plan[2] = {0, 0};            // radix plan of the FFT kernels: [0] FP64, [1] FP32
+  int plane_kind[2] = {0, 0};      // plane kernel variant (0..kPlaneKinds-1): [0] FP64, [1] FP32
 };
 
 // A set of vectors addressed through a slot list: vector for list entry c is
@@ -60,6 +63,7 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // LDS attributes of the plane kernels of grid N (call before any graph capture)
 void prepare_fft_kernels(int N);
 constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
+constexpr int kPlaneKinds = 2;       // plane kernels: workgroup form, wave form
 
 // ---- dense contractions on MFMA (FP64) ----
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)

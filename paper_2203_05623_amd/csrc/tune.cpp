@@ -1,10 +1,11 @@
-// Autotuner of a resident system: FFT radix plan (per precision) and the
-// split-K chunk of the projector GEMM, timed on the system's own slot batch.
+// Autotuner of a resident system: FFT radix plan and plane kernel variant (per
+// precision) and the split-K chunk of the projector GEMM, timed on the system's
+// own slot batch.
 //
 // Results are cached as JSON lines in the file named by STH_TUNE_CACHE (if
 // set), one object per line:
-//   {"key": "gfx950 N=72 npw=22575 nst=973 M=384 slots=2048", "plan64": 0,
-//    "plan32": 1, "kchunk": 2048}
+//   {"key": "gfx950 N=72 npw=22575 nst=973 M=384 slots=2048", "plan64": 1,
+//    "kind64": 1, "plan32": 1, "kind32": 0, "kchunk": 2048}
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -24,7 +25,13 @@ std::string tune_key(const System& s) {
   return buf;
 }
 
-bool cache_lookup(const std::string& key, int* p64, int* p32, int* kc) {
+struct Choice {
+  int plan[2] = {0, 0};
+  int kind[2] = {0, 0};
+  int kchunk = 0;
+};
+
+bool cache_lookup(const std::string& key, Choice* c) {
   const char* path = std::getenv("STH_TUNE_CACHE");
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -32,26 +39,34 @@ bool cache_lookup(const std::string& key, int* p64, int* p32, int* kc) {
   char line[512];
   bool found = false;
   const std::string pat = "\"key\": \"" + key + "\"";
+  auto field = [](const char* line, const char* name, int* out) {
+    const std::string tag = std::string("\"") + name + "\": %d";
+    const char* q = std::strstr(line, (std::string("\"") + name + "\":").c_str());
+    return q && std::sscanf(q, tag.c_str(), out) == 1;
+  };
   while (std::fgets(line, sizeof(line), f)) {
     if (!std::strstr(line, pat.c_str())) continue;
-    const char* q = std::strstr(line, "\"plan64\":");
-    const char* r = std::strstr(line, "\"plan32\":");
-    const char* t = std::strstr(line, "\"kchunk\":");
-    if (q && r && t && std::sscanf(q, "\"plan64\": %d", p64) == 1 &&
-        std::sscanf(r, "\"plan32\": %d", p32) == 1 && std::sscanf(t, "\"kchunk\": %d", kc) == 1)
-      found = true;   // the last matching line wins
+    Choice t;
+    if (field(line, "plan64", &t.plan[0]) && field(line, "kind64", &t.kind[0]) &&
+        field(line, "plan32", &t.plan[1]) && field(line, "kind32", &t.kind[1]) &&
+        field(line, "kchunk", &t.kchunk)) {
+      *c = t;   // the last matching line wins
+      found = true;
+    }
   }
   std::fclose(f);
   return found;
 }
 
-void cache_store(const std::string& key, int p64, int p32, int kc) {
+void cache_store(const std::string& key, const Choice& c) {
   const char* path = std::getenv("STH_TUNE_CACHE");
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"plan64\": %d, \"plan32\": %d, \"kchunk\": %d}\n",
-               key.c_str(), p64, p32, kc);
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"plan64\": %d, \"kind64\": %d, \"plan32\": %d, "
+               "\"kind32\": %d, \"kchunk\": %d}\n",
+               key.c_str(), c.plan[0], c.kind[0], c.plan[1], c.kind[1], c.kchunk);
   std::fclose(f);
 }
 
@@ -59,15 +74,22 @@ void cache_store(const std::string& key, int p64, int p32, int kc) {
 
 void Context::autotune(System& s) {
   const std::string key = tune_key(s);
-  int p64 = 0, p32 = 0, kc = s.kchunk;
-  if (cache_lookup(key, &p64, &p32, &kc) && p64 >= 0 && p64 < kRadixPlansHost && p32 >= 0 &&
-      p32 < kRadixPlansHost && kc >= s.kchunk) {
-    s.g.plan[0] = p64;
-    s.g.plan[1] = p32;
-    s.kchunk = kc;
-    s.nsplit = (s.npw + kc - 1) / kc;
-    s.tuned_from_cache = 1;
-    return;
+  Choice c;
+  if (cache_lookup(key, &c)) {
+    bool ok = c.kchunk >= s.kchunk;
+    for (int k = 0; k < 2; ++k)
+      ok = ok && c.plan[k] >= 0 && c.plan[k] < kRadixPlansHost && c.kind[k] >= 0 &&
+           c.kind[k] < kPlaneKinds;
+    if (ok) {
+      for (int k = 0; k < 2; ++k) {
+        s.g.plan[k] = c.plan[k];
+        s.g.plane_kind[k] = c.kind[k];
+      }
+      s.kchunk = c.kchunk;
+      s.nsplit = (s.npw + c.kchunk - 1) / c.kchunk;
+      s.tuned_from_cache = 1;
+      return;
+    }
   }
   // timing batch: the slot pool itself (zeroed), up to 256 columns
   const int n = std::min(s.nslots, 256);
@@ -91,31 +113,37 @@ void Context::autotune(System& s) {
   const int N = s.N;
   VecSet<z64> st64{s.d_sticks.as<z64>(), (long long)N * s.nst};
   VecSet<z32> st32{reinterpret_cast<z32*>(s.d_sticks.as<z64>()), (long long)N * s.nst};
-  int best[2] = {0, 0};
+  // FFT stages of H psi for every (radix plan, plane kernel) pair, per precision
   for (int k = 0; k < 2; ++k) {
     double bt = 1e300;
-    for (int p = 0; p < kRadixPlansHost; ++p) {
-      s.g.plan[k] = p;
-      const double ms = time_ms([&] {
-        if (k == 0) {
-          launch_zfft_inv<double, z64>(s.g, s.cvec(s.d_p), st64, dl, n, st_);
-          launch_plane_local<double>(s.g, st64, dl, n, s.d_vloc.as<double>(), nullptr, st_);
-          launch_zfft_fwd<double, z64>(s.g, {st64.base, st64.stride}, s.vec(s.d_q), dl, n,
-                                       ZF_PLAIN, {nullptr, 0}, nullptr, st_);
-        } else {
-          launch_zfft_inv<float, z64>(s.g, s.cvec(s.d_p), st32, dl, n, st_);
-          launch_plane_local<float>(s.g, st32, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
-          launch_zfft_fwd<float, z64>(s.g, {st32.base, st32.stride}, s.vec(s.d_q), dl, n,
-                                      ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+    int bp = 0, bkind = 0;
+    for (int kind = 0; kind < kPlaneKinds; ++kind) {
+      for (int p = 0; p < kRadixPlansHost; ++p) {
+        s.g.plan[k] = p;
+        s.g.plane_kind[k] = kind;
+        const double ms = time_ms([&] {
+          if (k == 0) {
+            launch_zfft_inv<double, z64>(s.g, s.cvec(s.d_p), st64, dl, n, st_);
+            launch_plane_local<double>(s.g, st64, dl, n, s.d_vloc.as<double>(), nullptr, st_);
+            launch_zfft_fwd<double, z64>(s.g, {st64.base, st64.stride}, s.vec(s.d_q), dl, n,
+                                         ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+          } else {
+            launch_zfft_inv<float, z64>(s.g, s.cvec(s.d_p), st32, dl, n, st_);
+            launch_plane_local<float>(s.g, st32, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
+            launch_zfft_fwd<float, z64>(s.g, {st32.base, st32.stride}, s.vec(s.d_q), dl, n,
+                                        ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+          }
+        });
+        s.tune_ms[6 * k + 2 * kind + p] = ms;
+        if (ms < bt) {
+          bt = ms;
+          bp = p;
+          bkind = kind;
         }
-      });
-      s.tune_ms[2 * k + p] = ms;
-      if (ms < bt) {
-        bt = ms;
-        best[k] = p;
       }
     }
-    s.g.plan[k] = best[k];
+    s.g.plan[k] = bp;
+    s.g.plane_kind[k] = bkind;
   }
   // split-K chunk of C = W^H P (the partial buffer was sized for the smallest)
   const int cand[3] = {s.kchunk, 2 * s.kchunk, 4 * s.kchunk};
@@ -129,7 +157,7 @@ void Context::autotune(System& s) {
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[4 + i] = ms;
+    s.tune_ms[12 + i] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;
@@ -139,7 +167,12 @@ void Context::autotune(System& s) {
   s.nsplit = (s.npw + bk - 1) / bk;
   STH_HIP_CHECK(hipEventDestroy(a));
   STH_HIP_CHECK(hipEventDestroy(b));
-  cache_store(key, s.g.plan[0], s.g.plan[1], s.kchunk);
+  for (int k = 0; k < 2; ++k) {
+    c.plan[k] = s.g.plan[k];
+    c.kind[k] = s.g.plane_kind[k];
+  }
+  c.kchunk = s.kchunk;
+  cache_store(key, c);
 }
 
 void Context::system_info(int id, sth_system_info* info) {
@@ -152,8 +185,10 @@ void Context::system_info(int id, sth_system_info* info) {
   info->nproj = s.nproj;
   info->fft_plan_fp64 = s.g.plan[0];
   info->fft_plan_fp32 = s.g.plan[1];
+  info->plane_kernel_fp64 = s.g.plane_kind[0];
+  info->plane_kernel_fp32 = s.g.plane_kind[1];
   info->gemm_kchunk = s.kchunk;
-  for (int i = 0; i < 8; ++i) info->tune_ms[i] = s.tune_ms[i];
+  for (int i = 0; i < 16; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
 }
 

@@ -37,13 +37,38 @@ def test_binding_covers_the_header():
     assert set(_declared()) == set(_lib.EXPORTS)
 
 
-def test_struct_layouts_match_header():
-    """Field offsets of the C structs (x86-64 SysV layout) as the binding sees them."""
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a C
+    compiler makes of include/sth.h (offsetof / sizeof printed by a small program
+    built with gcc against the header)."""
+    import shutil
+    import subprocess
     from paper_2203_05623_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [_lib.sth_config, _lib.sth_system_desc, _lib.sth_solve_opts,
+               _lib.sth_ticket_info, _lib.sth_system_info]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sth.h"',
+             "int main(void) {"]
+    want = []
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("%zu\\n", sizeof({name}));')
+        want.append(C.sizeof(st))
+        for fname, _ in st._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({name}, {fname}));')
+            want.append(getattr(st, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == want
     assert C.sizeof(_lib.sth_config) == 24
     assert _lib.sth_system_desc.ptr_kind.offset == 88
-    assert C.sizeof(_lib.sth_solve_opts) == 24
-    assert _lib.sth_ticket_info.op_applications_fp32.offset == 64
 
 
 def test_no_device_is_an_error_code(lib):

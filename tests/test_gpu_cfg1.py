@@ -175,18 +175,20 @@ def test_invalid_arguments_are_errors(sth, cfg1, sys1):
     assert e.value.code == P._lib.STH_E_NOT_FOUND
 
 
-def test_graph_replay_matches_direct_launches(cfg1):
+def test_graph_replay_matches_direct_launches(cfg1, tmp_path, monkeypatch):
     """With fewer slots than solves the server reaches the steady state where the
     captured hipGraph of CG iterations is replayed (with the server's own eager
     refills, retirements and synchronisations between replays).  The result must
-    equal, bit for bit, a run with direct launches (deterministic reductions)."""
-    import os
+    equal, bit for bit, a run with direct launches (deterministic reductions).
+    Both runs share one autotuner cache, so that they use the same FFT plans and
+    GEMM split (a timing-based choice could differ between two contexts)."""
     import paper_2203_05623_amd as P
     cfg, s, H, eps, Psi = cfg1
     dv = workloads.dv_block(cfg, range(cfg.npert))
     out = {}
+    monkeypatch.setenv("STH_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     for mode in ("1", "0"):
-        os.environ["STH_GRAPHS"] = mode
+        monkeypatch.setenv("STH_GRAPHS", mode)
         ctx = P.sth_create(device=0, max_slots=64)
         try:
             sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, Psi, eps)
@@ -201,7 +203,6 @@ def test_graph_replay_matches_direct_launches(cfg1):
                 P.sth_release_ticket(ctx, t)
         finally:
             P.sth_destroy(ctx)
-            os.environ.pop("STH_GRAPHS", None)
     for prec in (P.STH_FP64, P.STH_MIXED):
         xg, ng = out[("1", prec)]
         xd, nd = out[("0", prec)]
