@@ -144,9 +144,11 @@ typedef struct {
   int npw, nsticks, nslots, nv, nproj;
   int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
   int gemm_kchunk;                    /* split-K chunk of C = W^H P */
-  double tune_ms[16];                 /* timings behind the choice, ms per launch set:
+  double tune_ms[24];                 /* timings behind the choice, ms per launch set:
                                          [6 p + 2 kind + plan] for precision p (0 FP64,
-                                         1 FP32), [12 + i] kchunk candidate i < 3 */
+                                         1 FP32), [12 + i] split-K candidate i < 8
+                                         (32, 24, 16, 12, 11, 8, 6, 4 chunks, repeats
+                                         skipped) */
   int tuned_from_cache;
   int plane_kernel_fp64, plane_kernel_fp32;   /* plane kernel variant: 0 single-pass
                                                  workgroup per plane, 1 and 2 split

@@ -364,7 +364,10 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.g.kin = s.d_kin.as<double>();
   s.g.tw64 = s.d_tw64.as<z64>();
   s.g.tw32 = s.d_tw32.as<z32>();
-  s.kchunk = 2048;
+  // split-K chunk of C = W^H P: the smallest candidate of the autotuner (at most
+  // kMaxSplit chunks, a multiple of the 16-element LDS stage); the partial
+  // buffer is sized for it
+  s.kchunk = split_chunk(s.npw, kMaxSplit);
   s.nsplit = (s.npw + s.kchunk - 1) / s.kchunk;
   s.ntile = gemm_a_c_tiles(s.npw);
   s.nchunk = cg_chunks(s.npw);

@@ -16,6 +16,15 @@
 
 namespace sth {
 
+// split-K of C = W^H P: at most kMaxSplit chunks of K; chunk lengths are
+// multiples of the 16-element LDS stage of the GEMM kernel
+constexpr int kMaxSplit = 32;
+inline int split_chunk(int K, int nsplit) {
+  const int c = (K + nsplit - 1) / nsplit;
+  return ((c + 15) / 16) * 16;
+}
+
+
 double now_s();
 
 // Owning device allocation, charged against the context's HBM budget.
@@ -132,7 +141,7 @@ struct System {
 
   // hipGraph of `graph_nit` CG iterations over every slot (steady state), one per
   // operator precision; captured on first use, replayed each check period
-  double tune_ms[16] = {};         // autotuner timings (see sth_system_info)
+  double tune_ms[24] = {};         // autotuner timings (see sth_system_info)
   int tuned_from_cache = 0;
   DevMem d_ident;                  // [nslots] 0..nslots-1
   hipGraphExec_t graph[2] = {nullptr, nullptr};

@@ -91,8 +91,8 @@ void Context::autotune(System& s) {
       return;
     }
   }
-  // timing batch: the slot pool itself (zeroed), up to 256 columns
-  const int n = std::min(s.nslots, 256);
+  // timing batch: the whole slot pool (zeroed), the batch a CG step launches on
+  const int n = s.nslots;
   s.d_p.zero(st_);
   s.d_q.zero(st_);
   s.d_sticks.zero(st_);
@@ -145,19 +145,22 @@ void Context::autotune(System& s) {
     s.g.plan[k] = bp;
     s.g.plane_kind[k] = bkind;
   }
-  // split-K chunk of C = W^H P (the partial buffer was sized for the smallest)
-  const int cand[3] = {s.kchunk, 2 * s.kchunk, 4 * s.kchunk};
+  // split-K chunk of C = W^H P (the partial buffer was sized for the smallest):
+  // candidate split counts, so that the workgroup count can fill the 256 CUs evenly
+  const int nsplits[8] = {kMaxSplit, 24, 16, 12, 11, 8, 6, 4};
   double bt = 1e300;
-  int bk = s.kchunk;
-  for (int i = 0; i < 3; ++i) {
-    const int kci = cand[i];
+  int bk = s.kchunk, ncand = 0, prev = -1;
+  for (int i = 0; i < 8; ++i) {
+    const int kci = std::max(split_chunk(s.npw, nsplits[i]), s.kchunk);
+    if (kci == prev) continue;
+    prev = kci;
     const double ms = time_ms([&] {
       launch_gemm_ah_b(s.W(), s.npw, s.M, s.cvec(s.d_p), dl, n, s.npw, kci, s.d_part.as<z64>(),
                        st_);
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[12 + i] = ms;
+    s.tune_ms[12 + ncand++] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;
@@ -188,7 +191,7 @@ void Context::system_info(int id, sth_system_info* info) {
   info->plane_kernel_fp64 = s.g.plane_kind[0];
   info->plane_kernel_fp32 = s.g.plane_kind[1];
   info->gemm_kchunk = s.kchunk;
-  for (int i = 0; i < 16; ++i) info->tune_ms[i] = s.tune_ms[i];
+  for (int i = 0; i < 24; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
 }
 

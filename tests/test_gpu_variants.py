@@ -1,0 +1,119 @@
+"""GPU parity of every FFT-stage variant the autotuner can pick.
+
+The autotuner keeps the fastest (radix plan, plane kernel form) per precision, so
+a normal run exercises only one of them.  Here each pair is forced through the
+tuning cache (STH_TUNE_CACHE) and checked against the oracle: H.psi in FP64
+(1e-12 relative) and mixed-precision solves, whose inner operator uses the FP32
+variant (1e-6 relative on Delta psi at true residual 1e-8).  Config 1 (24^3,
+plans (8, 3) and (4, 6)) and the benchmark system (72^3, plans (8, 9) and (9, 8)).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1)]
+
+
+def _force(path, info, M, plan, kind):
+    key = (f"gfx950 N={info['N']} npw={info['npw']} nst={info['nsticks']} M={M} "
+           f"slots={info['nslots']}")
+    with open(path, "a") as f:
+        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "plan32": {plan}, '
+                f'"kind32": {kind}, "kchunk": {info["gemm_kchunk"]}}}\n')
+
+
+def _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
+    """Yields (plan, kind, system id) with the variant forced."""
+    base = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+    info = P.sth_system_info_get(ctx, base)
+    info["N"] = cfg.N
+    P.sth_release_system(ctx, base)
+    M = nv + s.beta.shape[0]
+    for plan, kind in VARIANTS:
+        path = tmp_path / f"tune_{plan}_{kind}.jsonl"
+        _force(path, info, M, plan, kind)
+        monkeypatch.setenv("STH_TUNE_CACHE", str(path))
+        sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+        got = P.sth_system_info_get(ctx, sid)
+        assert got["tuned_from_cache"] == 1
+        assert (got["fft_plan_fp64"], got["plane_kernel_fp64"]) == (plan, kind)
+        assert (got["fft_plan_fp32"], got["plane_kernel_fp32"]) == (plan, kind)
+        yield plan, kind, sid
+        P.sth_release_system(ctx, sid)
+    monkeypatch.delenv("STH_TUNE_CACHE")
+
+
+def test_variants_cfg1(cfg1_system, cfg1_dense, monkeypatch, tmp_path):
+    import paper_2203_05623_amd as P
+    cfg = workloads.get_config("cfg1")
+    s = cfg1_system
+    H, w, V = cfg1_dense
+    nv = cfg.nv
+    eps, psi = w[:nv], np.ascontiguousarray(V[:nv])
+    rng = np.random.default_rng(21)
+    c = rng.standard_normal((19, s.npw)) + 1j * rng.standard_normal((19, s.npw))
+    ref_h = oracle.apply_H(s, c)
+    dv = workloads.dv_block(cfg, range(2))
+    ref_x = np.array([[oracle.solve_lu(H, psi, eps[v], oracle.rhs(s, psi, v, dv[j]))
+                       for v in range(nv)] for j in range(2)])
+    ctx = P.sth_create(device=0, max_slots=64)
+    try:
+        for plan, kind, sid in _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
+            got = P.sth_apply_h(ctx, sid, c)
+            e_h = np.abs(got - ref_h).max() / np.abs(ref_h).max()
+            t = P.sth_submit_solves(ctx, sid, dv, np.arange(nv), tol=1e-8,
+                                    precision=P.STH_MIXED, want_dpsi=True)
+            assert P.sth_wait(ctx, t, 120.0)
+            x = np.empty((2, nv, s.npw), np.complex128)
+            P.sth_fetch_dpsi(ctx, t, x)
+            P.sth_release_ticket(ctx, t)
+            e_x = max(np.linalg.norm(x[j, v] - ref_x[j, v]) / np.linalg.norm(ref_x[j, v])
+                      for j in range(2) for v in range(nv))
+            print(f"cfg1 plan {plan} kind {kind}: H.psi {e_h:.2e}, mixed dpsi {e_x:.2e}")
+            assert e_h < 1e-12
+            assert e_x < 1e-6
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_variants_cfg2(monkeypatch, tmp_path):
+    import paper_2203_05623_amd as P
+    cfg = workloads.get_config("cfg2")
+    cache = os.path.join(ROOT, "tests", "_cache", f"cfg2_seed{cfg.seed_kb}_valence.npz")
+    if not os.path.exists(cache):
+        pytest.skip("oracle valence cache missing: run tests/golden/make_valence_cache.py cfg2")
+    d = np.load(cache)
+    s = oracle.build_system("cfg2")
+    nv = cfg.nv
+    eps, psi = d["eps"][:nv], d["psi"][:nv]
+    rng = np.random.default_rng(22)
+    c = rng.standard_normal((5, s.npw)) + 1j * rng.standard_normal((5, s.npw))
+    ref_h = oracle.apply_H(s, c)
+    j, v = 0, 127
+    dvj = workloads.dv_r(cfg, j)
+    ref_x, _, _, st = oracle.pcg_solve(s, psi, eps, v, oracle.rhs(s, psi, v, dvj), tol=1e-12)
+    assert st == 0
+    ctx = P.sth_create(device=0, max_slots=256)
+    try:
+        for plan, kind, sid in _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
+            got = P.sth_apply_h(ctx, sid, c)
+            e_h = np.abs(got - ref_h).max() / np.abs(ref_h).max()
+            t = P.sth_submit_solves(ctx, sid, dvj[None], np.array([v]), tol=1e-8,
+                                    precision=P.STH_MIXED, want_dpsi=True)
+            assert P.sth_wait(ctx, t, 120.0)
+            x = np.empty((1, 1, s.npw), np.complex128)
+            P.sth_fetch_dpsi(ctx, t, x)
+            P.sth_release_ticket(ctx, t)
+            e_x = np.linalg.norm(x[0, 0] - ref_x) / np.linalg.norm(ref_x)
+            print(f"cfg2 plan {plan} kind {kind}: H.psi {e_h:.2e}, mixed dpsi {e_x:.2e}")
+            assert e_h < 1e-12
+            assert e_x < 1e-6
+    finally:
+        P.sth_destroy(ctx)
