@@ -659,6 +659,160 @@ __attribute__((amdgpu_waves_per_eu(PlaneWave<N, P>::template waves_per_eu<T>()))
   tile_to_sticks<N, S::NT, T>(tile, g, row);
 }
 
+// ------------------------------------------------------------------ z sticks, wave form
+// The z-stick transforms with every stick owned by one wavefront (the lane
+// mapping and the passes of k_plane_wave along i2): a wave zero-fills, fills and
+// transforms its PW sticks with only wave-level ordering; the workgroup meets
+// once, around the transposed exchange with the [i0][stick] array.
+template <int N, int P, typename T>
+struct ZWave {
+  using S = PlaneWave<N, P>;
+  static constexpr int NWZ = sizeof(T) == 8 ? 5 : 10;   // waves per workgroup
+  static constexpr int ZS = NWZ * S::PW;                // sticks per workgroup
+  static constexpr int NT = NWZ * 64;
+  static constexpr int NP = N + 1;
+};
+
+template <int N, int P, typename T, typename Tin>
+__global__ __launch_bounds__((ZWave<N, P, T>::NT)) void k_zfft_inv_wave(GridDev g,
+                                                                       VecSet<const Tin> in,
+                                                                       VecSet<cpx<T>> sticks,
+                                                                       const int* slots) {
+  using Z = ZWave<N, P, T>;
+  using S = PlaneWave<N, P>;
+  constexpr int R1 = S::R1, R2 = S::R2, M1 = S::M1, M2 = S::M2, PW = S::PW;
+  constexpr int ZS = Z::ZS, NP = Z::NP, NT = Z::NT;
+  __shared__ cpx<T> buf[ZS * NP];
+  const int slot = slots[blockIdx.y];
+  const int s0 = blockIdx.x * ZS;
+  const int ns = min(ZS, g.nst - s0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane / PW, q = lane - j * PW;
+  const int sw = wave * PW;                    // first stick of the wave (local)
+  const int nw = max(0, min(PW, ns - sw));     // sticks of the wave
+  const cpx<T>* tw = twiddles<T>(g);
+  // zero-fill and fill the wave's sticks
+  for (int e = lane; e < nw * N; e += 64) {
+    const int st = e / N;
+    buf[(sw + st) * NP + (e - st * N)] = cpx<T>{T(0), T(0)};
+  }
+  wave_sync();
+  const Tin* src = in.base + slot * in.stride;
+  if (nw > 0) {
+    const int e0 = g.stick_off[s0 + sw], e1 = g.stick_off[s0 + sw + nw];
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const int pos = g.elem_pos[e];
+      const int st = pos / N - s0, i0 = pos - (pos / N) * N;
+      buf[st * NP + i0] = cvt<T>(src[e]);
+    }
+  }
+  wave_sync();
+  const bool live = q < nw;
+  const int st = sw + q;
+  cpx<T> v[R1];
+  if (live && j < M1) {
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = buf[st * NP + j + r * M1];
+  }
+  wave_sync();
+  if (live && j < M1) {
+    Dft<R1, +1, T>::run(v);
+#pragma unroll
+    for (int p = 0; p < R1; ++p) buf[st * NP + j * R1 + p] = v[p];
+  }
+  wave_sync();
+  if (live && j < M2) {
+    cpx<T> u[R2], w[R2];
+    pass_twiddles<R2>(tw, j, w);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) u[r] = buf[st * NP + j + r * M2];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) u[r] = u[r] * conj(w[r]);
+    Dft<R2, +1, T>::run(u);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) buf[st * NP + j + r * M2] = u[r];
+  }
+  __syncthreads();
+  cpx<T>* dst = sticks.base + slot * sticks.stride;
+  for (int t = threadIdx.x; t < N * ns; t += NT) {
+    const int i0 = t / ns, sl = t - i0 * ns;
+    dst[(long long)i0 * g.nst + s0 + sl] = buf[sl * NP + i0];
+  }
+}
+
+template <int N, int P, typename T, typename Tout>
+__global__ __launch_bounds__((ZWave<N, P, T>::NT)) void k_zfft_fwd_wave(
+    GridDev g, VecSet<const cpx<T>> sticks, VecSet<Tout> out, const int* slots, int mode,
+    VecSet<const Tout> pin, const double* eps_slot) {
+  using Z = ZWave<N, P, T>;
+  using S = PlaneWave<N, P>;
+  constexpr int R1 = S::R1, R2 = S::R2, M1 = S::M1, M2 = S::M2, PW = S::PW;
+  constexpr int ZS = Z::ZS, NP = Z::NP, NT = Z::NT;
+  __shared__ cpx<T> buf[ZS * NP];
+  const int slot = slots[blockIdx.y];
+  const int s0 = blockIdx.x * ZS;
+  const int ns = min(ZS, g.nst - s0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane / PW, q = lane - j * PW;
+  const int sw = wave * PW;
+  const int nw = max(0, min(PW, ns - sw));
+  const cpx<T>* tw = twiddles<T>(g);
+  const cpx<T>* src = sticks.base + slot * sticks.stride;
+  for (int t = threadIdx.x; t < N * ns; t += NT) {
+    const int i0 = t / ns, sl = t - i0 * ns;
+    buf[sl * NP + i0] = src[(long long)i0 * g.nst + s0 + sl];
+  }
+  __syncthreads();
+  // forward transform as the adjoint of the inverse passes: pass 2^H, pass 1^H
+  const bool live = q < nw;
+  const int st = sw + q;
+  if (live && j < M2) {
+    cpx<T> u[R2], w[R2];
+    pass_twiddles<R2>(tw, j, w);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) u[r] = buf[st * NP + j + r * M2];
+    Dft<R2, -1, T>::run(u);
+#pragma unroll
+    for (int r = 1; r < R2; ++r) u[r] = u[r] * w[r];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) buf[st * NP + j + r * M2] = u[r];
+  }
+  wave_sync();
+  cpx<T> v[R1];
+  if (live && j < M1) {
+#pragma unroll
+    for (int p = 0; p < R1; ++p) v[p] = buf[st * NP + j * R1 + p];
+  }
+  wave_sync();
+  if (live && j < M1) {
+    Dft<R1, -1, T>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) buf[st * NP + j + r * M1] = v[r];
+  }
+  wave_sync();
+  // the wave's sticks back to the sphere, with 1/N^3 and the kinetic / shift term
+  if (nw == 0) return;
+  const double inv_n3 = 1.0 / (double(N) * N * N);
+  Tout* dst = out.base + slot * out.stride;
+  const double eps = (mode == ZF_SHIFT) ? eps_slot[slot] : 0.0;
+  const Tout* p = (mode == ZF_SHIFT) ? pin.base + slot * pin.stride : nullptr;
+  const int e0 = g.stick_off[s0 + sw], e1 = g.stick_off[s0 + sw + nw];
+  for (int e = e0 + lane; e < e1; e += 64) {
+    const int pos = g.elem_pos[e];
+    const int sl = pos / N - s0, i0 = pos - (pos / N) * N;
+    const cpx<T> c = buf[sl * NP + i0];
+    double re = double(c.x) * inv_n3, im = double(c.y) * inv_n3;
+    if (mode == ZF_SHIFT) {
+      const double k = g.kin[e] - eps;
+      re += k * double(p[e].x);
+      im += k * double(p[e].y);
+    }
+    using TO = typename real_of<Tout>::type;
+    dst[e].x = TO(re);
+    dst[e].y = TO(im);
+  }
+}
+
 template <int N, int P, typename T>
 __global__ __launch_bounds__((pthreads<N, P>())) void k_plane_to_grid(
     GridDev g, VecSet<const cpx<T>> sticks, VecSet<cpx<T>> grid, const int* slots) {
@@ -756,15 +910,25 @@ int plan_of(const GridDev& g) { return g.plan[sizeof(T) == 4 ? 1 : 0]; }
     }                                                                                 \
   } while (0)
 
+// The z-stick kernels follow the form of the plane kernel (GridDev::plane_kind):
+// 0 workgroup form, 1 wave form.
 template <typename T, typename Tin>
 void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
                      const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
+  const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
-    constexpr int ZS = zsticks<NN, T>();
-    dim3 grid((g.nst + ZS - 1) / ZS, ncols);
-    hipLaunchKernelGGL((k_zfft_inv<NN, PP, T, Tin>), grid, dim3(zthreads<NN, PP, T>()), 0, st,
-                       g, in, sticks, slots);
+    if (kind == 0) {
+      constexpr int ZS = zsticks<NN, T>();
+      dim3 grid((g.nst + ZS - 1) / ZS, ncols);
+      hipLaunchKernelGGL((k_zfft_inv<NN, PP, T, Tin>), grid, dim3(zthreads<NN, PP, T>()), 0, st,
+                         g, in, sticks, slots);
+    } else {
+      using Z = ZWave<NN, PP, T>;
+      dim3 grid((g.nst + Z::ZS - 1) / Z::ZS, ncols);
+      hipLaunchKernelGGL((k_zfft_inv_wave<NN, PP, T, Tin>), grid, dim3(Z::NT), 0, st, g, in,
+                         sticks, slots);
+    }
   });
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -802,11 +966,19 @@ void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout>
                      const int* slots, int ncols, int mode, VecSet<const Tout> pin,
                      const double* eps_slot, hipStream_t st) {
   if (ncols <= 0) return;
+  const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
-    constexpr int ZS = zsticks<NN, T>();
-    dim3 grid((g.nst + ZS - 1) / ZS, ncols);
-    hipLaunchKernelGGL((k_zfft_fwd<NN, PP, T, Tout>), grid, dim3(zthreads<NN, PP, T>()), 0, st,
-                       g, sticks, out, slots, mode, pin, eps_slot);
+    if (kind == 0) {
+      constexpr int ZS = zsticks<NN, T>();
+      dim3 grid((g.nst + ZS - 1) / ZS, ncols);
+      hipLaunchKernelGGL((k_zfft_fwd<NN, PP, T, Tout>), grid, dim3(zthreads<NN, PP, T>()), 0, st,
+                         g, sticks, out, slots, mode, pin, eps_slot);
+    } else {
+      using Z = ZWave<NN, PP, T>;
+      dim3 grid((g.nst + Z::ZS - 1) / Z::ZS, ncols);
+      hipLaunchKernelGGL((k_zfft_fwd_wave<NN, PP, T, Tout>), grid, dim3(Z::NT), 0, st, g, sticks,
+                         out, slots, mode, pin, eps_slot);
+    }
   });
   STH_HIP_CHECK(hipGetLastError());
 }

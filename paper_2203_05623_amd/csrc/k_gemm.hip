@@ -50,9 +50,14 @@ constexpr int GTHR = 256;   // 4 waves, 2 x 2 arrangement of 32 x 32 sub-tiles
 template <typename T, typename S>
 __device__ inline cpx<T> rnd(const S& v) { return cpx<T>{T(v.x), T(v.y)}; }
 
+// waves per SIMD the register allocation is planned for (FP64: three workgroups
+// per CU; FP32: four, the most that stay free of spills)
+template <typename T>
+constexpr int gemm_wpe() { return sizeof(T) == 8 ? 3 : 4; }
+
 // part[s][c][m] = sum_{k in chunk s} conj(A[m][k]) B_c[k]   (accumulated in T)
 template <typename T, typename TB>
-__global__ __launch_bounds__(GTHR) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
+__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T>()))) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
                                                     VecSet<const TB> B, const int* slots,
                                                     int ncols, int K, int kchunk, cpx<T>* part) {
   using V4 = typename Mfma<T>::v4;
@@ -152,10 +157,10 @@ __global__ void k_reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M,
 }
 
 // Y_c[g] = s0 Y_c[g] + sum_m A[m][g] C[c][m]  (+ optional partial dots with dot_in).
-// Registers are budgeted for three workgroups per CU (measured: FP64 48 -> 55
-// TFLOP/s over the two-workgroup default).
+// The FP64 register budget for three workgroups per CU measured 55 TFLOP/s
+// against 48 with the compiler's two-workgroup default.
 template <typename T>
-__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_a_c(
+__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T>()))) void k_gemm_a_c(
     const cpx<T>* __restrict__ A, int lda, int M, const cpx<T>* __restrict__ C, VecSet<z64> Y,
     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots) {
   using V4 = typename Mfma<T>::v4;
