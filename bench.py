@@ -34,7 +34,7 @@ MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
 # (phase, precision) -> measured HBM bytes / algorithmic bytes of its kernel
 # (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
 # whenever the kernel changes
-HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0048}
+HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0042}
 
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
@@ -236,8 +236,9 @@ def main():
     sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
                            eps[:cfg.nv])
     tinfo = P.sth_system_info_get(ctx, sid)
-    tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "fft_plan_fp32",
-                                    "plane_kernel_fp32", "gemm_kchunk", "tuned_from_cache")}
+    tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "zfft_kernel_fp64",
+                                    "fft_plan_fp32", "plane_kernel_fp32", "zfft_kernel_fp32",
+                                    "gemm_kchunk", "tuned_from_cache")}
     tuning["tune_ms"] = [round(x, 4) for x in tinfo["tune_ms"]]
     prec = P.STH_FP64 if args.precision == "fp64" else P.STH_MIXED
     bands = np.arange(cfg.nv)

@@ -137,22 +137,24 @@ sth_status sth_set_system(sth_ctx* ctx, const sth_system_desc* desc, void* strea
 
 /* Shape and tuning of a resident system.  The autotuner times, once per system
  * (or reads from the JSON-lines cache named by the environment variable
- * STH_TUNE_CACHE), each pair (radix plan, plane kernel variant) of the FFT
- * stages in FP64 and FP32 and the split-K chunk of the projector GEMM on the
- * system's real slot batch, and keeps the fastest. */
+ * STH_TUNE_CACHE), each combination (radix plan, plane kernel form, z-stick
+ * kernel form) of the FFT stages in FP64 and FP32 and the split-K chunk of the
+ * projector GEMM on the system's full slot batch, and keeps the fastest. */
 typedef struct {
   int npw, nsticks, nslots, nv, nproj;
   int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
   int gemm_kchunk;                    /* split-K chunk of C = W^H P */
   double tune_ms[24];                 /* timings behind the choice, ms per launch set:
-                                         [6 p + 2 kind + plan] for precision p (0 FP64,
-                                         1 FP32), [12 + i] split-K candidate i < 8
-                                         (32, 24, 16, 12, 11, 8, 6, 4 chunks, repeats
-                                         skipped) */
+                                         [8 p + 4 zkind + 2 kind + plan] for precision p
+                                         (0 FP64, 1 FP32), [16 + i] split-K candidate
+                                         i < 8 (32, 24, 16, 12, 11, 8, 6, 4 chunks,
+                                         repeats skipped) */
   int tuned_from_cache;
-  int plane_kernel_fp64, plane_kernel_fp32;   /* plane kernel variant: 0 single-pass
-                                                 workgroup per plane, 1 and 2 split
-                                                 i1 stage (two / three workgroups per CU) */
+  int plane_kernel_fp64, plane_kernel_fp32;   /* plane kernel form ("kind"): 0 workgroup
+                                                 form, 1 wave form (every row / column
+                                                 owned by one wavefront) */
+  int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"), same
+                                                 two forms */
 } sth_system_info;
 sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 

@@ -59,7 +59,8 @@ class sth_system_info(C.Structure):
                 ("nproj", C.c_int), ("fft_plan_fp64", C.c_int), ("fft_plan_fp32", C.c_int),
                 ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 24),
                 ("tuned_from_cache", C.c_int), ("plane_kernel_fp64", C.c_int),
-                ("plane_kernel_fp32", C.c_int)]
+                ("plane_kernel_fp32", C.c_int), ("zfft_kernel_fp64", C.c_int),
+                ("zfft_kernel_fp32", C.c_int)]
 
 
 class SthError(RuntimeError):

@@ -910,13 +910,12 @@ int plan_of(const GridDev& g) { return g.plan[sizeof(T) == 4 ? 1 : 0]; }
     }                                                                                 \
   } while (0)
 
-// The z-stick kernels follow the form of the plane kernel (GridDev::plane_kind):
-// 0 workgroup form, 1 wave form.
+// z-stick kernel form (GridDev::zfft_kind): 0 workgroup form, 1 wave form.
 template <typename T, typename Tin>
 void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
                      const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
-  const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
+  const int kind = g.zfft_kind[sizeof(T) == 4 ? 1 : 0];
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     if (kind == 0) {
       constexpr int ZS = zsticks<NN, T>();
@@ -966,7 +965,7 @@ void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout>
                      const int* slots, int ncols, int mode, VecSet<const Tout> pin,
                      const double* eps_slot, hipStream_t st) {
   if (ncols <= 0) return;
-  const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
+  const int kind = g.zfft_kind[sizeof(T) == 4 ? 1 : 0];
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     if (kind == 0) {
       constexpr int ZS = zsticks<NN, T>();

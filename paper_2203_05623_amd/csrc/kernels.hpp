@@ -23,7 +23,8 @@ struct GridDev {
   const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
   const z32* tw32 = nullptr;       // [N] same, rounded to FP32
   int plan[2] = {0, 0};            // radix plan of the FFT kernels: [0] FP64, [1] FP32
-  int plane_kind[2] = {0, 0};      // plane kernel variant (0..kPlaneKinds-1): [0] FP64, [1] FP32
+  int plane_kind[2] = {0, 0};      // plane kernel form (0..kPlaneKinds-1): [0] FP64, [1] FP32
+  int zfft_kind[2] = {0, 0};       // z-stick kernel form (0..kPlaneKinds-1): [0] FP64, [1] FP32
 };
 
 // A set of vectors addressed through a slot list: vector for list entry c is
@@ -63,7 +64,7 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // LDS attributes of the plane kernels of grid N (call before any graph capture)
 void prepare_fft_kernels(int N);
 constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
-constexpr int kPlaneKinds = 2;       // plane kernels: workgroup form, wave form
+constexpr int kPlaneKinds = 2;       // plane / z-stick kernels: workgroup form, wave form
 
 // ---- dense contractions on MFMA (FP64) ----
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)

@@ -5,7 +5,7 @@
 // Results are cached as JSON lines in the file named by STH_TUNE_CACHE (if
 // set), one object per line:
 //   {"key": "gfx950 N=72 npw=22575 nst=973 M=384 slots=2048", "plan64": 1,
-//    "kind64": 1, "plan32": 1, "kind32": 0, "kchunk": 2048}
+//    "kind64": 1, "zkind64": 0, "plan32": 1, "kind32": 0, "zkind32": 1, "kchunk": 1888}
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -28,6 +28,7 @@ std::string tune_key(const System& s) {
 struct Choice {
   int plan[2] = {0, 0};
   int kind[2] = {0, 0};
+  int zkind[2] = {0, 0};
   int kchunk = 0;
 };
 
@@ -48,7 +49,8 @@ bool cache_lookup(const std::string& key, Choice* c) {
     if (!std::strstr(line, pat.c_str())) continue;
     Choice t;
     if (field(line, "plan64", &t.plan[0]) && field(line, "kind64", &t.kind[0]) &&
-        field(line, "plan32", &t.plan[1]) && field(line, "kind32", &t.kind[1]) &&
+        field(line, "zkind64", &t.zkind[0]) && field(line, "plan32", &t.plan[1]) &&
+        field(line, "kind32", &t.kind[1]) && field(line, "zkind32", &t.zkind[1]) &&
         field(line, "kchunk", &t.kchunk)) {
       *c = t;   // the last matching line wins
       found = true;
@@ -64,9 +66,10 @@ void cache_store(const std::string& key, const Choice& c) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   std::fprintf(f,
-               "{\"key\": \"%s\", \"plan64\": %d, \"kind64\": %d, \"plan32\": %d, "
-               "\"kind32\": %d, \"kchunk\": %d}\n",
-               key.c_str(), c.plan[0], c.kind[0], c.plan[1], c.kind[1], c.kchunk);
+               "{\"key\": \"%s\", \"plan64\": %d, \"kind64\": %d, \"zkind64\": %d, "
+               "\"plan32\": %d, \"kind32\": %d, \"zkind32\": %d, \"kchunk\": %d}\n",
+               key.c_str(), c.plan[0], c.kind[0], c.zkind[0], c.plan[1], c.kind[1], c.zkind[1],
+               c.kchunk);
   std::fclose(f);
 }
 
@@ -79,11 +82,12 @@ void Context::autotune(System& s) {
     bool ok = c.kchunk >= s.kchunk;
     for (int k = 0; k < 2; ++k)
       ok = ok && c.plan[k] >= 0 && c.plan[k] < kRadixPlansHost && c.kind[k] >= 0 &&
-           c.kind[k] < kPlaneKinds;
+           c.kind[k] < kPlaneKinds && c.zkind[k] >= 0 && c.zkind[k] < kPlaneKinds;
     if (ok) {
       for (int k = 0; k < 2; ++k) {
         s.g.plan[k] = c.plan[k];
         s.g.plane_kind[k] = c.kind[k];
+        s.g.zfft_kind[k] = c.zkind[k];
       }
       s.kchunk = c.kchunk;
       s.nsplit = (s.npw + c.kchunk - 1) / c.kchunk;
@@ -113,37 +117,43 @@ void Context::autotune(System& s) {
   const int N = s.N;
   VecSet<z64> st64{s.d_sticks.as<z64>(), (long long)N * s.nst};
   VecSet<z32> st32{reinterpret_cast<z32*>(s.d_sticks.as<z64>()), (long long)N * s.nst};
-  // FFT stages of H psi for every (radix plan, plane kernel) pair, per precision
+  // FFT stages of H psi for every (radix plan, plane kernel form, z-stick kernel
+  // form), per precision
   for (int k = 0; k < 2; ++k) {
     double bt = 1e300;
-    int bp = 0, bkind = 0;
-    for (int kind = 0; kind < kPlaneKinds; ++kind) {
-      for (int p = 0; p < kRadixPlansHost; ++p) {
-        s.g.plan[k] = p;
-        s.g.plane_kind[k] = kind;
-        const double ms = time_ms([&] {
-          if (k == 0) {
-            launch_zfft_inv<double, z64>(s.g, s.cvec(s.d_p), st64, dl, n, st_);
-            launch_plane_local<double>(s.g, st64, dl, n, s.d_vloc.as<double>(), nullptr, st_);
-            launch_zfft_fwd<double, z64>(s.g, {st64.base, st64.stride}, s.vec(s.d_q), dl, n,
-                                         ZF_PLAIN, {nullptr, 0}, nullptr, st_);
-          } else {
-            launch_zfft_inv<float, z64>(s.g, s.cvec(s.d_p), st32, dl, n, st_);
-            launch_plane_local<float>(s.g, st32, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
-            launch_zfft_fwd<float, z64>(s.g, {st32.base, st32.stride}, s.vec(s.d_q), dl, n,
-                                        ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+    int bp = 0, bkind = 0, bz = 0;
+    for (int zk = 0; zk < kPlaneKinds; ++zk) {
+      for (int kind = 0; kind < kPlaneKinds; ++kind) {
+        for (int p = 0; p < kRadixPlansHost; ++p) {
+          s.g.plan[k] = p;
+          s.g.plane_kind[k] = kind;
+          s.g.zfft_kind[k] = zk;
+          const double ms = time_ms([&] {
+            if (k == 0) {
+              launch_zfft_inv<double, z64>(s.g, s.cvec(s.d_p), st64, dl, n, st_);
+              launch_plane_local<double>(s.g, st64, dl, n, s.d_vloc.as<double>(), nullptr, st_);
+              launch_zfft_fwd<double, z64>(s.g, {st64.base, st64.stride}, s.vec(s.d_q), dl, n,
+                                           ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+            } else {
+              launch_zfft_inv<float, z64>(s.g, s.cvec(s.d_p), st32, dl, n, st_);
+              launch_plane_local<float>(s.g, st32, dl, n, s.d_vloc32.as<float>(), nullptr, st_);
+              launch_zfft_fwd<float, z64>(s.g, {st32.base, st32.stride}, s.vec(s.d_q), dl, n,
+                                          ZF_PLAIN, {nullptr, 0}, nullptr, st_);
+            }
+          });
+          s.tune_ms[8 * k + 4 * zk + 2 * kind + p] = ms;
+          if (ms < bt) {
+            bt = ms;
+            bp = p;
+            bkind = kind;
+            bz = zk;
           }
-        });
-        s.tune_ms[6 * k + 2 * kind + p] = ms;
-        if (ms < bt) {
-          bt = ms;
-          bp = p;
-          bkind = kind;
         }
       }
     }
     s.g.plan[k] = bp;
     s.g.plane_kind[k] = bkind;
+    s.g.zfft_kind[k] = bz;
   }
   // split-K chunk of C = W^H P (the partial buffer was sized for the smallest):
   // candidate split counts, so that the workgroup count can fill the 256 CUs evenly
@@ -160,7 +170,7 @@ void Context::autotune(System& s) {
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[12 + ncand++] = ms;
+    s.tune_ms[16 + ncand++] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;
@@ -173,6 +183,7 @@ void Context::autotune(System& s) {
   for (int k = 0; k < 2; ++k) {
     c.plan[k] = s.g.plan[k];
     c.kind[k] = s.g.plane_kind[k];
+    c.zkind[k] = s.g.zfft_kind[k];
   }
   c.kchunk = s.kchunk;
   cache_store(key, c);
@@ -190,6 +201,8 @@ void Context::system_info(int id, sth_system_info* info) {
   info->fft_plan_fp32 = s.g.plan[1];
   info->plane_kernel_fp64 = s.g.plane_kind[0];
   info->plane_kernel_fp32 = s.g.plane_kind[1];
+  info->zfft_kernel_fp64 = s.g.zfft_kind[0];
+  info->zfft_kernel_fp32 = s.g.zfft_kind[1];
   info->gemm_kchunk = s.kchunk;
   for (int i = 0; i < 24; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;

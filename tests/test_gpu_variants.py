@@ -1,8 +1,9 @@
 """GPU parity of every FFT-stage variant the autotuner can pick.
 
-The autotuner keeps the fastest (radix plan, plane kernel form) per precision, so
-a normal run exercises only one of them.  Here each pair is forced through the
-tuning cache (STH_TUNE_CACHE) and checked against the oracle: H.psi in FP64
+The autotuner keeps the fastest (radix plan, plane kernel form, z-stick kernel
+form) per precision, so a normal run exercises only one of them.  Here every radix
+plan and every kernel form of both stages is forced through the tuning cache
+(STH_TUNE_CACHE) in FP64 and in FP32 and checked against the oracle: H.psi in FP64
 (1e-12 relative) and mixed-precision solves, whose inner operator uses the FP32
 variant (1e-6 relative on Delta psi at true residual 1e-8).  Config 1 (24^3,
 plans (8, 3) and (4, 6)) and the benchmark system (72^3, plans (8, 9) and (9, 8)).
@@ -25,8 +26,9 @@ def _force(path, info, M, plan, kind):
     key = (f"gfx950 N={info['N']} npw={info['npw']} nst={info['nsticks']} M={M} "
            f"slots={info['nslots']}")
     with open(path, "a") as f:
-        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "plan32": {plan}, '
-                f'"kind32": {kind}, "kchunk": {info["gemm_kchunk"]}}}\n')
+        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "zkind64": {kind}, '
+                f'"plan32": {plan}, "kind32": {kind}, "zkind32": {1 - kind}, '
+                f'"kchunk": {info["gemm_kchunk"]}}}\n')
 
 
 def _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
@@ -43,8 +45,10 @@ def _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
         sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
         got = P.sth_system_info_get(ctx, sid)
         assert got["tuned_from_cache"] == 1
-        assert (got["fft_plan_fp64"], got["plane_kernel_fp64"]) == (plan, kind)
-        assert (got["fft_plan_fp32"], got["plane_kernel_fp32"]) == (plan, kind)
+        assert (got["fft_plan_fp64"], got["plane_kernel_fp64"], got["zfft_kernel_fp64"]) == \
+            (plan, kind, kind)
+        assert (got["fft_plan_fp32"], got["plane_kernel_fp32"], got["zfft_kernel_fp32"]) == \
+            (plan, kind, 1 - kind)
         yield plan, kind, sid
         P.sth_release_system(ctx, sid)
     monkeypatch.delenv("STH_TUNE_CACHE")
