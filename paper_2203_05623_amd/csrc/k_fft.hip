@@ -211,22 +211,25 @@ __device__ inline void plane_scatter(PlaneLds<N, T>& L, const GridDev& g, const 
   __syncthreads();
 }
 
-// w[r] = tw[r j] = exp(-2 pi i r j / N) for r < R.  FP64 reads every power from
-// the table (exact); FP32 reads w^1 and forms the other powers by a balanced
-// product tree (one load instead of R - 1, each power at most ceil(log2 R)
-// roundings deep).
+// w[r] = tw[r j] = exp(-2 pi i r j / N) for r < R: w^1 read from the table, the
+// other powers formed by a balanced product tree (one memory load instead of
+// R - 1; each power is at most ceil(log2 R) products deep, a few ulp).
 template <int R, typename T>
 __device__ inline void pass_twiddles(const cpx<T>* tw, int j, cpx<T>* w) {
   w[0] = cpx<T>{T(1), T(0)};
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (R > 1) w[1] = tw[j];
 #pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = tw[r * j];
-  } else {
-    if constexpr (R > 1) w[1] = tw[j];
-#pragma unroll
-    for (int r = 2; r < R; ++r) w[r] = w[r / 2] * w[r - r / 2];
-  }
+  for (int r = 2; r < R; ++r) w[r] = w[r / 2] * w[r - r / 2];
 }
+
+// Whether cell i2 of row i1 holds a stick (bit masks of the rows, N <= 128).
+struct RowBits {
+  unsigned long long lo, hi;
+  __device__ RowBits(const GridDev& g, int i1) : lo(g.rowbits[2 * i1]), hi(g.rowbits[2 * i1 + 1]) {}
+  __device__ bool operator()(int i2) const {
+    return ((i2 < 64 ? lo >> i2 : hi >> (i2 - 64)) & 1ull) != 0;
+  }
+};
 
 // The stick row of plane i0 into the tile (coalesced reads; cells without a
 // stick keep stale values, the first pass reads them as zero), and back.
@@ -297,7 +300,6 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
   cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
   const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
   const cpx<T>* tw = twiddles<T>(g);
-  const int* idx = g.idx12;
   const int nrow = g.nrow;
 
   sticks_to_tile<N, NT, T>(tile, g, row);
@@ -311,10 +313,11 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       if (t < nrow * M1) {
         const int f = t / M1, j = t - f * M1;
         const int i1 = g.row_list[f];
+        const RowBits has(g, i1);
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
           v[q][r] = cpx<T>{T(0), T(0)};
-          if (idx[i1 * N + j + r * M1] >= 0) v[q][r] = tile[i1 * NP + j + r * M1];
+          if (has(j + r * M1)) v[q][r] = tile[i1 * NP + j + r * M1];
         }
       }
     }
@@ -521,7 +524,6 @@ __attribute__((amdgpu_waves_per_eu(PlaneWave<N, P>::template waves_per_eu<T>()))
   cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
   const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
   const cpx<T>* tw = twiddles<T>(g);
-  const int* idx = g.idx12;
   const int nrow = g.nrow;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // lane = j * PW + q: butterfly j of transform q of the wave's group
@@ -541,10 +543,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWave<N, P>::template waves_per_eu<T>()))
     const int ig = a1 ? g.row_list[fg] : 0;
     cpx<T> v[R1];
     if (a1) {
+      const RowBits has(g, ig);
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         v[r] = cpx<T>{T(0), T(0)};
-        if (idx[ig * N + jg + r * M1] >= 0) v[r] = tile[ig * NP + jg + r * M1];
+        if (has(jg + r * M1)) v[r] = tile[ig * NP + jg + r * M1];
       }
     }
     wave_sync();
