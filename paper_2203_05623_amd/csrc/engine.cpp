@@ -336,14 +336,11 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.d_stick_i12 = upload(&budget_, sb.stick_i12, st_);
   s.d_row_list = upload(&budget_, sb.row_list, st_);
   {
-    std::vector<int> idx12((size_t)N * N, -1);
     std::vector<unsigned long long> bits((size_t)N * 2, 0ull);
     for (int k = 0; k < s.nst; ++k) {
       const int p = sb.stick_i12[k], i1 = p / N, i2 = p % N;
-      idx12[p] = k;
       bits[2 * i1 + (i2 >> 6)] |= 1ull << (i2 & 63);
     }
-    s.d_idx12 = upload(&budget_, idx12, st_);
     s.d_rowbits = upload(&budget_, bits, st_);
   }
   s.d_kin = upload(&budget_, sb.kin, st_);
@@ -365,7 +362,6 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.g.elem_pos = s.d_elem_pos.as<int>();
   s.g.stick_i12 = s.d_stick_i12.as<int>();
   s.g.row_list = s.d_row_list.as<int>();
-  s.g.idx12 = s.d_idx12.as<int>();
   s.g.rowbits = s.d_rowbits.as<unsigned long long>();
   for (int r : sb.row_list) s.g.rowmask[r >> 6] |= 1ull << (r & 63);
   s.g.kin = s.d_kin.as<double>();

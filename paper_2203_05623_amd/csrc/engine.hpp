@@ -114,7 +114,7 @@ struct System {
   int N = 0, npw = 0, nst = 0, nrow = 0, nv = 0, nproj = 0, M = 0;
   double L = 0.0, omega = 0.0, fs = 2.0, alpha_pv = 0.0;
   GridDev g;
-  DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_idx12, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
+  DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
   DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
   DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
   DevMem d_vloc;       // [N^3] double

@@ -17,7 +17,6 @@ struct GridDev {
   const int* elem_pos = nullptr;   // [npw] stick * N + i0 of each element
   const int* stick_i12 = nullptr;  // [nst] i1 * N + i2 of each stick
   const int* row_list = nullptr;   // [nrow] active i1 rows
-  const int* idx12 = nullptr;      // [N * N] stick at (i1, i2), -1 where there is none
   const unsigned long long* rowbits = nullptr;  // [N][2] bit i2 set: (i1, i2) holds a stick
   unsigned long long rowmask[3] = {0, 0, 0};  // bit i1: row i1 is active (N <= 192)
   const double* kin = nullptr;     // [npw] |G|^2 / 2
