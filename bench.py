@@ -35,6 +35,10 @@ MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
 # (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
 # whenever the kernel changes
 HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0042}
+# --precision: FP64 solves; mixed (FP32 inner operator, FP32-MFMA projector
+# GEMMs); mixed-bf16 (FP32 inner operator, BF16-MFMA hi/lo projector GEMMs)
+PRECISIONS = {"fp64": lambda P: P.STH_FP64, "mixed": lambda P: P.STH_MIXED,
+              "mixed-bf16": lambda P: P.STH_MIXED_BF16}
 
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
@@ -108,7 +112,7 @@ def served(args):
                              setup_s=time.perf_counter() - t0)
         print(f"{name}: setup {systems[name]['setup_s']:.1f} s, gap {systems[name]['gap']:.4f} Ha",
               file=sys.stderr, flush=True)
-    prec = P.STH_MIXED if args.precision == "mixed" else P.STH_FP64
+    prec = PRECISIONS[args.precision](P)
 
     def submit(name):
         s = systems[name]
@@ -174,7 +178,7 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--npert", type=int, default=0, help="override the perturbation count")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--slots", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
@@ -240,7 +244,7 @@ def main():
                                     "fft_plan_fp32", "plane_kernel_fp32", "zfft_kernel_fp32",
                                     "gemm_kchunk", "tuned_from_cache")}
     tuning["tune_ms"] = [round(x, 4) for x in tinfo["tune_ms"]]
-    prec = P.STH_FP64 if args.precision == "fp64" else P.STH_MIXED
+    prec = PRECISIONS[args.precision](P)
     bands = np.arange(cfg.nv)
     dv = torch.from_numpy(dv).to("cuda:0")      # inputs resident in HBM before timing
 
@@ -309,7 +313,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32/f64",
+        "dtype": {"fp64": "f64", "mixed": "f32/f64", "mixed-bf16": "bf16x2/f32/f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {cfg.natoms}-atom synthetic crystal, {cfg.N}^3 grid, "
                                f"{len(miller)} plane waves, {cfg.nv} bands, {cfg.nproj} KB "

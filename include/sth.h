@@ -65,8 +65,11 @@ enum { STH_PTR_HOST = 0, STH_PTR_DEVICE = 1 };
 /* Precision of a solve.  STH_FP64: everything in FP64.  STH_MIXED: FP32
  * FFTs / H.psi inside the CG iterations with FP64 recurrences, residuals and
  * P_c; the returned solution always meets tol on the true FP64 residual
- * (paper, Section 4.3 and 5.1: FP32 FFTs and communication, FP64 elsewhere). */
-enum { STH_FP64 = 0, STH_MIXED = 1 };
+ * (paper, Section 4.3 and 5.1: FP32 FFTs and communication, FP64 elsewhere).
+ * The projector / P_v GEMMs of that inner operator run on FP32 MFMA
+ * (STH_MIXED) or on BF16 MFMA with FP32 accumulation, each FP32 operand split
+ * into a bf16 high and low part (STH_MIXED_BF16). */
+enum { STH_FP64 = 0, STH_MIXED = 1, STH_MIXED_BF16 = 2 };
 
 /* Per-solve status codes returned by sth_fetch_stats. */
 enum {
@@ -102,7 +105,7 @@ typedef struct {
 typedef struct {
   double tol;               /* relative true residual ||b - A x|| / ||b|| to reach */
   int maxit;                /* CG iterations per solve (0 = 1000) */
-  int precision;            /* STH_FP64 or STH_MIXED */
+  int precision;            /* STH_FP64, STH_MIXED or STH_MIXED_BF16 */
   int want_dpsi;            /* keep dpsi for sth_fetch_dpsi */
 } sth_solve_opts;
 
@@ -115,7 +118,7 @@ typedef struct {
   double t_submit, t_start, t_done;   /* seconds on the library's monotonic clock */
   long long cg_iterations;  /* sum of CG iterations over finished solves */
   long long op_applications;/* operator applications incl. true-residual checks */
-  long long op_applications_fp32; /* of which with the FP32 inner operator (STH_MIXED) */
+  long long op_applications_fp32; /* of which with the FP32 inner operator (mixed forms) */
   long long graph_replays;  /* hipGraph replays of captured CG iterations on the ticket's
                                system so far (steady state with every slot busy) */
 } sth_ticket_info;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsth.so")
 STH_OK, STH_E_INVALID, STH_E_NOMEM, STH_E_AGAIN, STH_E_NOT_READY = 0, -1, -2, -3, -4
 STH_E_DEVICE, STH_E_NOT_FOUND, STH_E_INTERNAL = -5, -6, -7
 STH_PTR_HOST, STH_PTR_DEVICE = 0, 1
-STH_FP64, STH_MIXED = 0, 1
+STH_FP64, STH_MIXED, STH_MIXED_BF16 = 0, 1, 2
 SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",

@@ -407,6 +407,8 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   // FP32 copies for the inner operator of mixed-precision solves (rounded once)
   s.d_W32 = DevMem(&budget_, (size_t)s.M * s.npw * sizeof(z32));
   launch_z64_to_z32(s.d_W.as<z64>(), s.d_W32.as<z32>(), (long long)s.M * s.npw, st_);
+  s.d_Wb = DevMem(&budget_, 2 * (size_t)s.M * bf16_ldw(s.npw) * sizeof(bz));
+  launch_split_w(s.d_W32.as<z32>(), s.M, s.npw, bf16_ldw(s.npw), s.d_Wb.as<bz>(), st_);
   s.d_vloc32 = DevMem(&budget_, n3 * sizeof(float));
   launch_to_f32(s.d_vloc.as<double>(), s.d_vloc32.as<float>(), n3, st_);
   STH_HIP_CHECK(hipStreamSynchronize(st_));
@@ -566,9 +568,9 @@ static double plane_flops(const System& s, int n) {
 // out = (H - eps_slot) in + W diag W^H in, on the listed vectors (slot pool
 // scratch: sticks, part, C).  With `dots`, partial Re<in, out> per 64-row tile.
 void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                       bool dots, bool fp32) {
-  if (fp32) {
-    apply_op32(s, in, out, dl, n, dots);
+                       bool dots, int mode) {
+  if (mode != OP_FP64) {
+    apply_op32(s, in, out, dl, n, dots, mode == OP_BF16);
     return;
   }
   const int N = s.N;
@@ -603,7 +605,7 @@ void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const i
 // (inner iterations of mixed-precision solves); the kinetic and shift terms
 // and every vector in memory stay FP64.
 void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                         bool dots) {
+                         bool dots, bool bf16) {
   const int N = s.N;
   const double vb = double(s.npw) * sizeof(z64), sb = double(N) * s.nst * sizeof(z32);
   const double gf = 8.0 * s.M * double(s.npw) * n;
@@ -621,14 +623,22 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
                               s.ss.eps, st_);
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   h = prof_begin(PH_GEMM_AHB);
-  launch_gemm_ah_b(s.d_W32.as<z32>(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, part, st_);
+  if (bf16)
+    launch_gemm_ah_b_bf16(s.d_Wb.as<bz>(), bf16_ldw(s.npw), s.M, in, dl, n, s.npw, s.kchunk, part,
+                          st_);
+  else
+    launch_gemm_ah_b(s.d_W32.as<z32>(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, part, st_);
   prof_end(h, s.M * vb / 2 + n * vb, gf);
   h = prof_begin(PH_REDUCE);
   launch_reduce_parts(part, s.nsplit, n, s.M, s.d_diag.as<double>(), 1.0, C, st_);
   prof_end(h, (s.nsplit + 1.0) * n * s.M * sizeof(z32), 0.0);
   h = prof_begin(PH_GEMM_AC);
-  launch_gemm_a_c(s.d_W32.as<z32>(), s.npw, s.M, C, out, dl, n, s.npw, 1.0, in,
-                  dots ? s.d_dots.as<double>() : nullptr, st_);
+  if (bf16)
+    launch_gemm_a_c_bf16(s.d_Wb.as<bz>(), bf16_ldw(s.npw), s.M, C, out, dl, n, s.npw, 1.0, in,
+                         dots ? s.d_dots.as<double>() : nullptr, st_);
+  else
+    launch_gemm_a_c(s.d_W32.as<z32>(), s.npw, s.M, C, out, dl, n, s.npw, 1.0, in,
+                    dots ? s.d_dots.as<double>() : nullptr, st_);
   prof_end(h, s.M * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
 }
 
@@ -777,8 +787,10 @@ uint64_t Context::submit(int id, int npert, const double* dv, int nband, const i
     set_error("submit: npert > 0, nband > 0, dv_r and bands required");
     throw Error(STH_E_INVALID);
   }
-  if (!(o.tol > 0.0) || o.maxit < 0 || (o.precision != STH_FP64 && o.precision != STH_MIXED)) {
-    set_error("submit: tol > 0, maxit >= 0 and precision STH_FP64/STH_MIXED required");
+  if (!(o.tol > 0.0) || o.maxit < 0 ||
+      (o.precision != STH_FP64 && o.precision != STH_MIXED && o.precision != STH_MIXED_BF16)) {
+    set_error("submit: tol > 0, maxit >= 0 and precision STH_FP64 / STH_MIXED / "
+              "STH_MIXED_BF16 required");
     throw Error(STH_E_INVALID);
   }
   std::lock_guard<std::mutex> glk(gpu_mu_);
@@ -1050,7 +1062,7 @@ void Context::refill(System& s) {
       h_ekin[slot] = s.ekin[v];
       h_tol[slot] = r->tol;
       h_maxit[slot] = r->maxit;
-      h_prec[slot] = r->precision == STH_MIXED ? 1 : 0;
+      h_prec[slot] = r->precision != STH_FP64 ? 1 : 0;
       h_pp[slot] = r->d_dv.as<double>() + j * n3;
       fresh.push_back(slot);
       band.push_back(v);
@@ -1098,9 +1110,9 @@ void Context::refill(System& s) {
 // One CG iteration on the listed slots: q = A p (FP64 or FP32 operator) with
 // <p, q> partials, alpha, x/r update with <r, K r> and ||r||^2, beta and the
 // convergence test, p = K r + beta p.
-void Context::cg_step(System& s, const int* dl, int n, bool fp32) {
+void Context::cg_step(System& s, const int* dl, int n, int mode) {
   const double vb = double(s.npw) * sizeof(z64);
-  apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, true, fp32);
+  apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, true, mode);
   const int h = prof_begin(PH_CG);
   launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl, n, s.ss, st_);
   launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl, n, s.ss,
@@ -1111,23 +1123,24 @@ void Context::cg_step(System& s, const int* dl, int n, bool fp32) {
 }
 
 void Context::iterate(System& s, const std::vector<int>& act, int nit) {
-  // slots of FP64 solves and of mixed-precision solves (FP32 inner operator)
-  // iterate as two batches; partial sums are indexed by list position, so each
-  // batch runs its whole CG step before the other starts
-  std::vector<int> lists[2];
-  for (int slot : act)
-    lists[s.slots[slot].req->precision == STH_MIXED ? 1 : 0].push_back(slot);
-  // steady state: every slot holds a solve of one precision -> replay the
-  // captured graph of nit iterations over the identity list (kernels skip slots
-  // that are no longer ACTIVE).  The per-kernel profiler needs direct launches.
-  const int kall = lists[0].empty() ? 1 : (lists[1].empty() ? 0 : -1);
+  // slots grouped by operator form (FP64, FP32 inner operator with FP32 or BF16
+  // projector GEMMs) iterate as separate batches; partial sums are indexed by
+  // list position, so each batch runs its whole CG step before the next starts
+  std::vector<int> lists[3];
+  for (int slot : act) lists[s.slots[slot].req->precision].push_back(slot);
+  // steady state: every slot holds a solve of one form -> replay the captured
+  // graph of nit iterations over the identity list (kernels skip slots that are
+  // no longer ACTIVE).  The per-kernel profiler needs direct launches.
+  int kall = -1;
+  for (int k = 0; k < 3; ++k)
+    if (int(lists[k].size()) == int(act.size())) kall = k;
   if (use_graphs_ && !prof_on_ && kall >= 0 && int(act.size()) == s.nslots) {
     if (!s.graph[kall] || s.graph_nit[kall] != nit) {
       if (s.graph[kall]) STH_HIP_CHECK(hipGraphExecDestroy(s.graph[kall]));
       s.graph[kall] = nullptr;
       hipGraph_t gr = nullptr;
       STH_HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
-      for (int it = 0; it < nit; ++it) cg_step(s, s.d_ident.as<int>(), s.nslots, kall == 1);
+      for (int it = 0; it < nit; ++it) cg_step(s, s.d_ident.as<int>(), s.nslots, kall);
       STH_HIP_CHECK(hipStreamEndCapture(st_, &gr));
       STH_HIP_CHECK(hipGraphInstantiate(&s.graph[kall], gr, nullptr, nullptr, 0));
       STH_HIP_CHECK(hipGraphDestroy(gr));
@@ -1136,17 +1149,17 @@ void Context::iterate(System& s, const std::vector<int>& act, int nit) {
     STH_HIP_CHECK(hipGraphLaunch(s.graph[kall], st_));
     s.graph_replays += 1;
   } else {
-    int* dl[2] = {nullptr, nullptr};
-    for (int k = 0; k < 2; ++k)
+    int* dl[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < 3; ++k)
       if (!lists[k].empty()) dl[k] = upload_list(s, lists[k]);
     for (int it = 0; it < nit; ++it)
-      for (int k = 0; k < 2; ++k)
-        if (!lists[k].empty()) cg_step(s, dl[k], int(lists[k].size()), k == 1);
+      for (int k = 0; k < 3; ++k)
+        if (!lists[k].empty()) cg_step(s, dl[k], int(lists[k].size()), k);
   }
   std::lock_guard<std::mutex> lk(mu_);
   for (int slot : act) {
     s.slots[slot].req->op_apps += nit;
-    if (s.slots[slot].req->precision == STH_MIXED) s.slots[slot].req->op32_apps += nit;
+    if (s.slots[slot].req->precision != STH_FP64) s.slots[slot].req->op32_apps += nit;
   }
 }
 

@@ -19,6 +19,12 @@ namespace sth {
 // split-K of C = W^H P: at most kMaxSplit chunks of K; chunk lengths are
 // multiples of the 16-element LDS stage of the GEMM kernel
 constexpr int kMaxSplit = 32;
+
+// Forms of the operator A = H - eps + alpha P_v a CG step applies: the FP64
+// operator, the FP32 inner operator with FP32-MFMA projector GEMMs, and the FP32
+// inner operator with BF16-MFMA (hi/lo) projector GEMMs; index of a solve's
+// precision (STH_FP64, STH_MIXED, STH_MIXED_BF16).
+enum OpMode : int { OP_FP64 = 0, OP_FP32 = 1, OP_BF16 = 2 };
 inline int split_chunk(int K, int nsplit) {
   const int c = (K + nsplit - 1) / nsplit;
   return ((c + 15) / 16) * 16;
@@ -119,6 +125,7 @@ struct System {
   DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
   DevMem d_vloc;       // [N^3] double
   DevMem d_W32;        // FP32 copy of W (inner operator of mixed-precision solves)
+  DevMem d_Wb;         // bf16 high and low planes of W, rows of bf16_ldw(npw) (STH_MIXED_BF16)
   DevMem d_vloc32;     // FP32 copy of V_loc
   DevMem d_psir;       // [nv][N^3] z64, psi_v(r) without Omega^{-1/2}
   DevMem d_eps_band;   // [nv]
@@ -144,8 +151,8 @@ struct System {
   double tune_ms[24] = {};         // autotuner timings (see sth_system_info)
   int tuned_from_cache = 0;
   DevMem d_ident;                  // [nslots] 0..nslots-1
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  int graph_nit[2] = {0, 0};
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  int graph_nit[3] = {0, 0, 0};
   long long graph_replays = 0;
   ~System() {
     for (auto& gx : graph)
@@ -219,14 +226,15 @@ class Context {
   void admit(System& s);
   void refill(System& s);
   void iterate(System& s, const std::vector<int>& act, int nit);
-  void cg_step(System& s, const int* dl, int n, bool fp32);   // one CG iteration (launches only)
+  // one CG iteration (launches only); mode: operator form (OP_FP64, OP_FP32, OP_BF16)
+  void cg_step(System& s, const int* dl, int n, int mode);
   void check_and_retire(System& s, std::vector<int>& act);
   void finish_drho(System& s);
   int* upload_list(System& s, const std::vector<int>& v);
   void apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                bool dots, bool fp32 = false);
+                bool dots, int mode = OP_FP64);
   void apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
-                  bool dots);
+                  bool dots, bool bf16);
   void order_after(hipStream_t user);   // library stream waits for the user's stream
   void order_before(hipStream_t user);  // user's stream waits for the library stream
   void alloc_slots(System& s, int nslots);

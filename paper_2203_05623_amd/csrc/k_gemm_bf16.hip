@@ -1,0 +1,334 @@
+// Projector GEMMs of the mixed-precision inner operator on BF16 matrix cores.
+//
+// Each FP32 operand x is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi)
+// (16 significant bits together) and a product is taken as
+// a_lo b_hi + a_hi b_lo + a_hi b_hi on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation; the dropped a_lo b_lo term is below 2^-16 relative.  W is split
+// once per system (two bf16 planes, rows padded to bf16_ldw(K) complex, so that
+// 16-B loads stay aligned and every tile and LDS stage stays inside a row);
+// the CG vectors (FP64 in memory) and the small FP32 coefficient block C are
+// split while they are staged in LDS.  The complex product uses the same
+// interleaved reduction index as the FP64/FP32 kernels: k' = 2k + t, t = 0 for
+// the real part, 1 for the imaginary part.
+//
+// v_mfma_f32_16x16x32_bf16 lane layout (64 lanes, l = lane), measured on gfx950:
+//   A[i][k]: i = l % 16, k = 8 (l / 16) + e (e < 8 bf16 values per lane);
+//   B[k][j]: k = 8 (l / 16) + e, j = l % 16;  D[i][j], register v: i = 4 (l / 16) + v, j = l % 16.
+#include "errors.hpp"
+#include "kernels.hpp"
+
+namespace sth {
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BT = 64;        // tile rows and columns
+constexpr int BK = 32;        // complex reduction elements per LDS stage (two MFMA k-steps)
+constexpr int BKP = BK + 4;   // LDS row pitch in complex (144 B: 16-B aligned, bank-spread)
+constexpr int BTHR = 256;     // 4 waves, 2 x 2 arrangement of 32 x 32 sub-tiles
+
+__device__ inline f4 mfma(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// hi / lo parts of a complex FP32 value
+__device__ inline void split(float re, float im, bz& hi, bz& lo) {
+  hi.x = __bf16(re);
+  hi.y = __bf16(im);
+  lo.x = __bf16(re - float(hi.x));
+  lo.y = __bf16(im - float(hi.y));
+}
+
+__device__ inline bf8 ld8(const bz* p) { return *reinterpret_cast<const bf8*>(p); }
+
+// (x0, y0, x1, y1, ...) -> (y0, -x0, y1, -x1, ...)
+__device__ inline bf8 swap_neg_odd(bf8 v) {
+  bf8 w = __builtin_shufflevector(v, v, 1, 0, 3, 2, 5, 4, 7, 6);
+#pragma unroll
+  for (int e = 1; e < 8; e += 2) w[e] = -w[e];
+  return w;
+}
+// (x0, y0, ...) -> (x0, -y0, ...)
+__device__ inline bf8 neg_odd(bf8 v) {
+#pragma unroll
+  for (int e = 1; e < 8; e += 2) v[e] = -v[e];
+  return v;
+}
+// (x0, y0, ...) -> (y0, x0, ...)
+__device__ inline bf8 swap(bf8 v) { return __builtin_shufflevector(v, v, 1, 0, 3, 2, 5, 4, 7, 6); }
+
+// three-product accumulation of one 16 x 16 tile
+__device__ inline f4 acc3(bf8 a_hi, bf8 a_lo, bf8 b_hi, bf8 b_lo, f4 c) {
+  c = mfma(a_lo, b_hi, c);
+  c = mfma(a_hi, b_lo, c);
+  return mfma(a_hi, b_hi, c);
+}
+
+// part[s][c][m] = sum_{k in chunk s} conj(W[m][k]) B_c[k]
+// (registers budgeted for three workgroups per CU in both kernels)
+__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_ah_b_bf16(
+    const bz* __restrict__ Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
+    const int* slots, int ncols, int K, int kchunk, z32* part) {
+  __shared__ bz As[2][BT][BKP];
+  __shared__ bz Bs[2][BT][BKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * BT, n0 = blockIdx.y * BT, s = blockIdx.z;
+  const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
+  const int kq = lane >> 4, r16 = lane & 15;
+  f4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
+  // staging: W as 16-B chunks (4 complex) of both planes, 4 per thread; the
+  // vectors as single complex values, 8 per thread
+  const z64* bcol[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int n = n0 + (tid + i * BTHR) / BK;
+    bcol[i] = (n < ncols) ? B.base + (long long)slots[n] * B.stride : nullptr;
+  }
+  uint4 rw[4];
+  z64 rb[8];
+  auto fetch = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c >> 9, row = (c & 511) >> 3, k4 = (c & 7) * 4;
+      const int m = m0 + row;
+      const bz* src = Wb + pl * wplane + (long long)m * ldw + kb + k4;
+      rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int kk = (tid + i * BTHR) % BK, k = kb + kk;
+      rb[i] = (bcol[i] && k < kend) ? bcol[i][k] : z64{0.0, 0.0};
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int kb = kbeg; kb < kend; kb += BK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c >> 9, row = (c & 511) >> 3, k4 = (c & 7) * 4;
+      *reinterpret_cast<uint4*>(&As[pl][row][k4]) = rw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * BTHR, col = e / BK, kk = e % BK;
+      split(float(rb[i].x), float(rb[i].y), Bs[0][col][kk], Bs[1][col][kk]);
+    }
+    __syncthreads();
+    if (kb + BK < kend) fetch(kb + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int k0 = ks * 16 + 4 * kq;
+      bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ah[t] = ld8(&As[0][wm * 32 + t * 16 + r16][k0]);
+        al[t] = ld8(&As[1][wm * 32 + t * 16 + r16][k0]);
+        bh[t] = ld8(&Bs[0][wn * 32 + t * 16 + r16][k0]);
+        bl[t] = ld8(&Bs[1][wn * 32 + t * 16 + r16][k0]);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          // Re = sum W.x P.x + W.y P.y;  Im = sum W.x P.y - W.y P.x
+          accr[x][y] = acc3(ah[x], al[x], bh[y], bl[y], accr[x][y]);
+          acci[x][y] = acc3(ah[x], al[x], swap_neg_odd(bh[y]), swap_neg_odd(bl[y]), acci[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 32 + x * 16 + 4 * kq + v;
+        const int n = n0 + wn * 32 + y * 16 + r16;
+        if (m < M && n < ncols)
+          part[((long long)s * ncols + n) * M + m] = z32{accr[x][y][v], acci[x][y][v]};
+      }
+}
+
+// Y_c[g] = s0 Y_c[g] + sum_m W[m][g] C[c][m]  (+ optional partial dots with dot_in)
+__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_a_c_bf16(
+    const bz* __restrict__ Wb, long long wplane, int ldw, int M, const z32* __restrict__ C,
+    VecSet<z64> Y, const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
+    double* dots) {
+  __shared__ bz As[2][BT][BKP];   // [plane][g][m]: W staged transposed
+  __shared__ bz Cs[2][BT][BKP];   // [plane][column][m]
+  __shared__ double red[2][BT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wg = wave & 1, wn = wave >> 1;
+  const int g0 = blockIdx.x * BT, n0 = blockIdx.y * BT;
+  const int kq = lane >> 4, r16 = lane & 15;
+  f4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
+  // staging: W rows m (both planes) as 16-B chunks of 4 consecutive g, 4 per
+  // thread, written transposed; C as single complex values, 8 per thread
+  uint4 rw[4];
+  z32 rc[8];
+  auto fetch = [&](int mb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c >> 9, mm = (c & 511) >> 4, g4 = (c & 15) * 4;
+      const int m = mb + mm;
+      const bz* src = Wb + pl * wplane + (long long)m * ldw + g0 + g4;
+      rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
+      const int n = n0 + col, m = mb + mm;
+      rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : z32{0.f, 0.f};
+    }
+  };
+  if (M > 0) fetch(0);
+  for (int mb = 0; mb < M; mb += BK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c >> 9, mm = (c & 511) >> 4, g4 = (c & 15) * 4;
+      const bz* q = reinterpret_cast<const bz*>(&rw[i]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) As[pl][g4 + u][mm] = q[u];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
+      split(rc[i].x, rc[i].y, Cs[0][col][mm], Cs[1][col][mm]);
+    }
+    __syncthreads();
+    if (mb + BK < M) fetch(mb + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int k0 = ks * 16 + 4 * kq;
+      bf8 ah[2], al[2], ch[2], cl[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ah[t] = ld8(&As[0][wg * 32 + t * 16 + r16][k0]);
+        al[t] = ld8(&As[1][wg * 32 + t * 16 + r16][k0]);
+        ch[t] = ld8(&Cs[0][wn * 32 + t * 16 + r16][k0]);
+        cl[t] = ld8(&Cs[1][wn * 32 + t * 16 + r16][k0]);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          // Re = sum W.x C.x - W.y C.y;  Im = sum W.x C.y + W.y C.x
+          accr[x][y] = acc3(ah[x], al[x], neg_odd(ch[y]), neg_odd(cl[y]), accr[x][y]);
+          acci[x][y] = acc3(ah[x], al[x], swap(ch[y]), swap(cl[y]), acci[x][y]);
+        }
+    }
+    __syncthreads();
+  }
+  double dsum[2] = {0.0, 0.0};
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int n = n0 + wn * 32 + y * 16 + r16;
+    if (n >= ncols) continue;
+    z64* yrow = Y.base + (long long)slots[n] * Y.stride;
+    const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gg = g0 + wg * 32 + x * 16 + 4 * kq + v;
+        if (gg < K) {
+          z64 o = {double(accr[x][y][v]), double(acci[x][y][v])};
+          if (s0 != 0.0) {   // s0 == 0 never reads Y (it may be uninitialised)
+            const z64 yo = yrow[gg];
+            o.x += s0 * yo.x;
+            o.y += s0 * yo.y;
+          }
+          yrow[gg] = o;
+          if (drow) {
+            const z64 d = drow[gg];
+            dsum[y] += d.x * o.x + d.y * o.y;
+          }
+        }
+      }
+  }
+  if (!dots) return;
+  // sum over the 4 lane groups that share a column, then over the two g halves
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    dsum[y] += __shfl_xor(dsum[y], 16);
+    dsum[y] += __shfl_xor(dsum[y], 32);
+  }
+  if (wg == 1 && kq == 0) {
+    red[0][wn * 32 + r16] = dsum[0];
+    red[1][wn * 32 + r16] = dsum[1];
+  }
+  __syncthreads();
+  if (wg == 0 && kq == 0) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int n = n0 + wn * 32 + y * 16 + r16;
+      if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y] + red[y][wn * 32 + r16];
+    }
+  }
+}
+
+// both bf16 planes of W (FP32 source, rows of K complex) with rows padded to ldw
+__global__ void k_split_w(const z32* __restrict__ W, int M, int K, int ldw, bz* Wb,
+                          long long wplane) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)M * ldw) return;
+  const int m = int(i / ldw), g = int(i - (long long)m * ldw);
+  const z32 v = g < K ? W[(long long)m * K + g] : z32{0.f, 0.f};
+  split(v.x, v.y, Wb[i], Wb[wplane + i]);
+}
+
+}  // namespace
+
+void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st) {
+  const long long n = (long long)M * ldw;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_split_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, M, K,
+                     ldw, Wb, n);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_gemm_ah_b_bf16(const bz* Wb, int ldw, int M, VecSet<const z64> B, const int* slots,
+                           int ncols, int K, int kchunk, z32* part, hipStream_t st) {
+  if (ncols <= 0 || M <= 0) return;
+  if (ldw != bf16_ldw(K) || kchunk % 4 != 0) {
+    set_error("bf16 GEMM: row pitch %d (want %d), K chunk %d (multiple of 4)", ldw, bf16_ldw(K),
+              kchunk);
+    throw Error(STH_E_INTERNAL);
+  }
+  const int nsplit = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + BT - 1) / BT, (ncols + BT - 1) / BT, nsplit);
+  hipLaunchKernelGGL(k_gemm_ah_b_bf16, grid, dim3(BTHR), 0, st, Wb, (long long)M * ldw, ldw, M, B,
+                     slots, ncols, K, kchunk, part);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+void launch_gemm_a_c_bf16(const bz* Wb, int ldw, int M, const z32* C, VecSet<z64> Y,
+                          const int* slots, int ncols, int K, double s0,
+                          VecSet<const z64> dot_in, double* dots, hipStream_t st) {
+  if (ncols <= 0) return;
+  if (ldw != bf16_ldw(K)) {
+    set_error("bf16 GEMM: row pitch %d (want %d)", ldw, bf16_ldw(K));
+    throw Error(STH_E_INTERNAL);
+  }
+  dim3 grid(gemm_a_c_tiles(K), (ncols + BT - 1) / BT);
+  hipLaunchKernelGGL(k_gemm_a_c_bf16, grid, dim3(BTHR), 0, st, Wb, (long long)M * ldw, ldw, M, C,
+                     Y, slots, ncols, K, s0, dot_in, dots);
+  STH_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace sth

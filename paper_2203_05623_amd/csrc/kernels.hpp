@@ -90,6 +90,21 @@ void launch_gemm_a_c(const z32* A, int lda, int M, const z32* C, VecSet<z64> Y,
 void launch_z64_to_z32(const z64* src, z32* dst, long long n, hipStream_t st);
 inline int gemm_a_c_tiles(int K) { return (K + 63) / 64; }
 
+// BF16 variants for the inner operator of STH_MIXED_BF16 solves: W held as two
+// bf16 planes (hi, lo) of rows padded to ldw complex, products
+// a_lo b_hi + a_hi b_lo + a_hi b_hi with FP32 accumulation (k_gemm_bf16.hip)
+struct bz {
+  __bf16 x, y;
+};
+// row pitch of the bf16 planes: a multiple of 64 with a full LDS stage of slack
+inline int bf16_ldw(int K) { return ((K + 63) / 64) * 64 + 64; }
+void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st);
+void launch_gemm_ah_b_bf16(const bz* Wb, int ldw, int M, VecSet<const z64> B, const int* slots,
+                           int ncols, int K, int kchunk, z32* part, hipStream_t st);
+void launch_gemm_a_c_bf16(const bz* Wb, int ldw, int M, const z32* C, VecSet<z64> Y,
+                          const int* slots, int ncols, int K, double s0,
+                          VecSet<const z64> dot_in, double* dots, hipStream_t st);
+
 // ---- CG vector kernels (FP64) ----
 struct SlotState {
   double* rho;       // [nslots] <r, K r>

@@ -103,22 +103,25 @@ def test_valence_lobpcg_matches_dense(sth, cfg1, cfg1_dense):
     assert np.abs(psi.conj() @ psi.T - np.eye(NV + 1)).max() < 1e-12
 
 
-def test_mixed_precision_matches_oracle(sth, cfg1, sys1):
-    """Mixed precision on the tiny crystal (FP32 FFT / H.psi / projector GEMMs inside CG,
-    FP64 residuals and defect correction): true residual 1e-8, Delta psi and chi0
+@pytest.mark.parametrize("form", ["mixed", "mixed-bf16"])
+def test_mixed_precision_matches_oracle(sth, cfg1, sys1, form):
+    """Mixed precision on the tiny crystal (FP32 FFT / H.psi inside CG with the
+    projector GEMMs on FP32 MFMA, or on BF16 MFMA with hi/lo split operands; FP64
+    residuals and defect correction): true residual 1e-8, Delta psi and chi0
     eigenvalues within 1e-6 of the FP64 oracle."""
     P, ctx = sth
     cfg, s, H, eps, Psi = cfg1
     npert = cfg.npert
     dv = workloads.dv_block(cfg, range(npert))
-    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(NV), tol=1e-8, precision=P.STH_MIXED,
+    prec = P.STH_MIXED if form == "mixed" else P.STH_MIXED_BF16
+    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(NV), tol=1e-8, precision=prec,
                             want_dpsi=True)
     assert P.sth_wait(ctx, t, 120.0)
     info = P.sth_poll(ctx, t)
     dpsi = np.empty((npert, NV, s.npw), np.complex128)
     P.sth_fetch_dpsi(ctx, t, dpsi)
     iters, resid, status, lat = P.sth_fetch_stats(ctx, t, npert * NV)
-    print("mixed: iters mean", iters.mean(), "op apps", info["op_applications"],
+    print(form, ": iters mean", iters.mean(), "op apps", info["op_applications"],
           "fp32", info["op_applications_fp32"], "max resid", resid.max())
     assert np.all(status == 0) and resid.max() <= 1e-8
     assert info["op_applications_fp32"] > 0
@@ -127,13 +130,13 @@ def test_mixed_precision_matches_oracle(sth, cfg1, sys1):
         B = np.stack([oracle.rhs(s, Psi, v, dv[j]) for j in range(npert)], 1)
         X[:, v] = oracle.solve_lu(H, Psi, eps[v], B).T
     rel = np.linalg.norm(dpsi - X, axis=2) / np.linalg.norm(X, axis=2)
-    print("mixed dpsi max rel err", rel.max())
+    print(form, "dpsi max rel err", rel.max())
     assert rel.max() < 1e-6
     dn_ref = np.stack([oracle.drho(s, Psi, X[j]) for j in range(npert)])
     M, S, lam = P.sth_chi0_block(ctx, t, npert)
     lam_ref, _, _ = oracle.chi0_block(s, dv, dn_ref)
     err = np.abs(lam - lam_ref).max() / np.abs(lam_ref).max()
-    print("mixed chi0 eigenvalue rel err", err)
+    print(form, "chi0 eigenvalue rel err", err)
     assert err < 1e-6
     P.sth_release_ticket(ctx, t)
 
@@ -192,7 +195,7 @@ def test_graph_replay_matches_direct_launches(cfg1, tmp_path, monkeypatch):
         ctx = P.sth_create(device=0, max_slots=64)
         try:
             sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, Psi, eps)
-            for prec in (P.STH_FP64, P.STH_MIXED):
+            for prec in (P.STH_FP64, P.STH_MIXED, P.STH_MIXED_BF16):
                 t = P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-10, precision=prec,
                                         want_dpsi=True)
                 assert P.sth_wait(ctx, t, 120.0)
@@ -203,7 +206,7 @@ def test_graph_replay_matches_direct_launches(cfg1, tmp_path, monkeypatch):
                 P.sth_release_ticket(ctx, t)
         finally:
             P.sth_destroy(ctx)
-    for prec in (P.STH_FP64, P.STH_MIXED):
+    for prec in (P.STH_FP64, P.STH_MIXED, P.STH_MIXED_BF16):
         xg, ng = out[("1", prec)]
         xd, nd = out[("0", prec)]
         print("precision", prec, "graph replays", ng, "direct", nd)

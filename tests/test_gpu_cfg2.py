@@ -75,13 +75,14 @@ def oracle_samples(ref):
     return {jv: _oracle_dpsi(s, eps, psi, *jv, tol=1e-12) for jv in SAMPLES}
 
 
-@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6)])
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6),
+                                                 ("mixed-bf16", 1e-8, 1e-6)])
 def test_sampled_solves_match_oracle(sth, ref, sys2, oracle_samples, precision, tol, bound):
     P, ctx = sth
     s, eps, psi = ref
     npert = 2
     dv = workloads.dv_block(CFG, range(npert))
-    prec = P.STH_FP64 if precision == "fp64" else P.STH_MIXED
+    prec = {"fp64": P.STH_FP64, "mixed": P.STH_MIXED, "mixed-bf16": P.STH_MIXED_BF16}[precision]
     t = P.sth_submit_solves(ctx, sys2, dv, np.arange(CFG.nv), tol=tol, precision=prec,
                             want_dpsi=True)
     assert P.sth_wait(ctx, t, 300.0)
