@@ -34,7 +34,9 @@ MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
 # (phase, precision) -> measured HBM bytes / algorithmic bytes of its kernel
 # (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
 # whenever the kernel changes
-HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0042}
+HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0045,
+                        # both mixed forms run the same plane kernels
+                        ("plane", "mixed"): 1.0088, ("plane", "mixed-bf16"): 1.0088}
 # --precision: FP64 solves; mixed (FP32 inner operator, FP32-MFMA projector
 # GEMMs); mixed-bf16 (FP32 inner operator, BF16-MFMA hi/lo projector GEMMs)
 PRECISIONS = {"fp64": lambda P: P.STH_FP64, "mixed": lambda P: P.STH_MIXED,
