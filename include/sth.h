@@ -88,7 +88,7 @@ typedef struct {
 
 typedef struct {
   double L;                 /* cubic cell edge (bohr) */
-  int n;                    /* FFT grid points per axis: 24, 48, 72 or 96 */
+  int n;                    /* FFT grid points per axis: 24, 48, 72, 96 or 144 */
   int npw;                  /* plane waves in the wave-function sphere */
   const int32_t* miller;    /* [npw][3]; host memory always; must satisfy 4 max|m_i| + 1 <= n */
   const double* vloc_r;     /* [n^3] local potential (Ha) */
@@ -147,17 +147,21 @@ typedef struct {
   int npw, nsticks, nslots, nv, nproj;
   int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
   int gemm_kchunk;                    /* split-K chunk of C = W^H P */
-  double tune_ms[24];                 /* timings behind the choice, ms per launch set:
-                                         [8 p + 4 zkind + 2 kind + plan] for precision p
-                                         (0 FP64, 1 FP32), [16 + i] split-K candidate
-                                         i < 8 (32, 24, 16, 12, 11, 8, 6, 4 chunks,
-                                         repeats skipped) */
+  double tune_ms[32];                 /* timings behind the choice, ms per launch set:
+                                         [12 p + 6 zkind + 2 kind + plan] for precision p
+                                         (0 FP64, 1 FP32), 0 where not timed; [24 + i]
+                                         split-K candidate i < 8 (32, 24, 16, 12, 11, 8,
+                                         6, 4 chunks, repeats skipped) */
   int tuned_from_cache;
   int plane_kernel_fp64, plane_kernel_fp32;   /* plane kernel form ("kind"): 0 workgroup
                                                  form, 1 wave form (every row / column
-                                                 owned by one wavefront) */
-  int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"), same
-                                                 two forms */
+                                                 owned by one wavefront), 2 strip form
+                                                 (the plane in strips of rows and columns
+                                                 through a scratch plane; the only form
+                                                 of grids above 96, whose plane tile
+                                                 exceeds the LDS) */
+  int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"): 0
+                                                 workgroup form, 1 wave form */
 } sth_system_info;
 sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 
@@ -174,7 +178,9 @@ sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* 
  * are ignored (nv may be 0), by block LOBPCG on the device with FP64
  * Rayleigh-Ritz.  eps_out [nbands], psi_out complex128 [nbands][npw] (caller
  * order), both in `out_ptr_kind` memory.  Converged when every residual
- * ||H x - theta x|| <= tol.  *iters and *max_resid report the run. */
+ * ||H x - theta x|| <= tol.  *iters and *max_resid report the run.  With the
+ * environment variable STH_VERBOSE=1 each iteration prints one progress line
+ * (iteration, largest residual, elapsed seconds) to stderr. */
 sth_status sth_valence(sth_ctx* ctx, const sth_system_desc* desc, int nbands, double tol,
                        int maxit, double* eps_out, double* psi_out, int out_ptr_kind,
                        double* max_resid, int* iters);

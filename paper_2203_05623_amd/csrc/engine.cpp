@@ -336,11 +336,13 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.d_stick_i12 = upload(&budget_, sb.stick_i12, st_);
   s.d_row_list = upload(&budget_, sb.row_list, st_);
   {
+    // two words per row: read only by the tile forms (N <= kTileMaxN)
     std::vector<unsigned long long> bits((size_t)N * 2, 0ull);
-    for (int k = 0; k < s.nst; ++k) {
-      const int p = sb.stick_i12[k], i1 = p / N, i2 = p % N;
-      bits[2 * i1 + (i2 >> 6)] |= 1ull << (i2 & 63);
-    }
+    if (N <= 128)
+      for (int k = 0; k < s.nst; ++k) {
+        const int p = sb.stick_i12[k], i1 = p / N, i2 = p % N;
+        bits[2 * i1 + (i2 >> 6)] |= 1ull << (i2 & 63);
+      }
     s.d_rowbits = upload(&budget_, bits, st_);
   }
   s.d_kin = upload(&budget_, sb.kin, st_);
@@ -367,6 +369,11 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.g.kin = s.d_kin.as<double>();
   s.g.tw64 = s.d_tw64.as<z64>();
   s.g.tw32 = s.d_tw32.as<z32>();
+  // scratch planes of the strip-form plane kernels (sized for FP64)
+  s.d_stage = DevMem(&budget_, (size_t)kStageSlots * s.nrow * N * sizeof(z64));
+  s.g.stage = s.d_stage.as<void>();
+  s.g.stage_slots = kStageSlots;
+  prepare_fft_kernels(N);
   // split-K chunk of C = W^H P: the smallest candidate of the autotuner (at most
   // kMaxSplit chunks, a multiple of the 16-element LDS stage); the partial
   // buffer is sized for it
@@ -423,8 +430,8 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
               "beta/dij when nproj>0, nv < npw)");
     throw Error(STH_E_INVALID);
   }
-  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96) {
-    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96)", d.n);
+  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96 && d.n != 144) {
+    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96, 144)", d.n);
     throw Error(STH_E_INVALID);
   }
   std::lock_guard<std::mutex> glk(gpu_mu_);

@@ -121,6 +121,7 @@ struct System {
   double L = 0.0, omega = 0.0, fs = 2.0, alpha_pv = 0.0;
   GridDev g;
   DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
+  DevMem d_stage;      // [kStageSlots][nrow][N] z64 scratch planes of the strip-form kernels
   DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
   DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
   DevMem d_vloc;       // [N^3] double
@@ -148,7 +149,7 @@ struct System {
 
   // hipGraph of `graph_nit` CG iterations over every slot (steady state), one per
   // operator precision; captured on first use, replayed each check period
-  double tune_ms[24] = {};         // autotuner timings (see sth_system_info)
+  double tune_ms[32] = {};         // autotuner timings (see sth_system_info)
   int tuned_from_cache = 0;
   DevMem d_ident;                  // [nslots] 0..nslots-1
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};

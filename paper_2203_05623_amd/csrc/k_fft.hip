@@ -19,6 +19,8 @@
 // is chosen per system and precision (GridDev::plan, set by the autotuner).
 // Workgroups have as many threads as the widest pass has butterflies, so each
 // pass is one round of work between two barriers.
+#include <algorithm>
+
 #include "errors.hpp"
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -33,7 +35,9 @@ constexpr size_t kLdsBytes = 160 * 1024;   // LDS per CU on gfx950
 // would exceed 40 KB
 template <int N, typename T>
 constexpr int zsticks() {
-  return (64 * (N + 1) * int(sizeof(cpx<T>)) > 40960) ? 32 : 64;
+  int z = 64;
+  while (z > 8 && z * (N + 1) * int(sizeof(cpx<T>)) > 40960) z /= 2;
+  return z;
 }
 template <int N, int P, typename T>
 constexpr int zthreads() {
@@ -878,6 +882,261 @@ __global__ __launch_bounds__((pthreads<N, P>())) void k_drho(GridDev g, const z6
   }
 }
 
+// ------------------------------------------------------------------ planes in strips
+// Plane form for grids whose N x (N + 1) tile exceeds the LDS (N = 144: 334 KB
+// in FP64), also selectable on the smaller grids.  A plane is processed in
+// strips: strips of active rows for the transforms along i2 and strips of CC
+// columns for the transforms along i1, passed through a scratch plane
+// Y[nrow][N] (active rows only) in global memory.  The grid is persistent: at
+// most g.stage_slots workgroups, each looping over planes with its own scratch
+// plane, so the scratch of the whole grid (stage_slots x nrow x N values) is
+// rewritten in place and stays in the caches.  Each strip is read and written
+// coalesced (rows: consecutive i2; columns: runs of CC consecutive i2).
+constexpr size_t kStripTileBudget = 58 * 1024;   // LDS of a strip tile: two workgroups per CU
+// rows per strip (an alias-free sphere has at most N/2 active rows)
+template <int N, typename T>
+constexpr int strip_rows() {
+  int r = N / 2;
+  while (r > 1 && size_t(r) * (N + 1) * sizeof(cpx<T>) > kStripTileBudget) --r;
+  return r;
+}
+// columns per strip: the largest divisor of N whose strip fits
+template <int N, typename T>
+constexpr int strip_cols() {
+  int c = N;
+  while (c > 1 && (N % c != 0 || size_t(N) * (c + 1) * sizeof(cpx<T>) > kStripTileBudget)) --c;
+  return c;
+}
+template <int N, typename T>
+struct Strips {
+  static constexpr int NT = 512;
+  static constexpr int NP = N + 1;
+  static constexpr int RC = strip_rows<N, T>();
+  static constexpr int CC = strip_cols<N, T>();
+  static constexpr int CP = CC + 1;               // LDS pitch of a column strip
+  static constexpr int NCS = N / CC;              // column strips of a plane
+  static constexpr size_t tile_elems = size_t(RC) * NP > size_t(N) * CP ? size_t(RC) * NP
+                                                                         : size_t(N) * CP;
+  static constexpr size_t tile_bytes = tile_elems * sizeof(cpx<T>);
+  static constexpr size_t lds_bytes = tile_bytes + N * sizeof(cpx<T>) + N * sizeof(int);
+};
+
+// LDS of a strip-form workgroup: strip tile, twiddles, row index (i1 -> position
+// in the active-row list, -1 for an empty row).
+template <int N, typename T>
+struct StripLds {
+  cpx<T>* tile;
+  cpx<T>* tw;
+  int* rowidx;
+  __device__ StripLds(unsigned char* raw, const GridDev& g) {
+    using S = Strips<N, T>;
+    tile = reinterpret_cast<cpx<T>*>(raw);
+    tw = reinterpret_cast<cpx<T>*>(raw + S::tile_bytes);
+    rowidx = reinterpret_cast<int*>(raw + S::tile_bytes + N * sizeof(cpx<T>));
+    stage_twiddles<T, S::NT>(tw, twiddles<T>(g), N);
+    for (int i = threadIdx.x; i < N; i += S::NT) rowidx[i] = -1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < g.nrow; i += S::NT) rowidx[g.row_list[i]] = i;
+    __syncthreads();
+  }
+};
+
+// stick row of a plane -> inverse along i2 on the active rows -> Y
+template <int N, int P, typename T>
+__device__ inline void strips_rows_inverse(const StripLds<N, T>& L, const GridDev& g,
+                                           const cpx<T>* row, cpx<T>* Y) {
+  using S = Strips<N, T>;
+  constexpr int NT = S::NT, NP = S::NP, RC = S::RC;
+  for (int r0 = 0; r0 < g.nrow; r0 += RC) {
+    const int nr = min(RC, g.nrow - r0);
+    for (int i = threadIdx.x; i < nr * NP; i += NT) L.tile[i] = cpx<T>{T(0), T(0)};
+    __syncthreads();
+    for (int s = threadIdx.x; s < g.nst; s += NT) {
+      const int p = g.stick_i12[s];
+      const int i1 = p / N;
+      const int rr = L.rowidx[i1] - r0;
+      if (rr >= 0 && rr < nr) L.tile[rr * NP + (p - i1 * N)] = row[s];
+    }
+    __syncthreads();
+    RadixPlan<N, P>::template fft<T, +1, NT, RC>::run(
+        L.tile, nr, 1, [](int f) { return f * NP; }, L.tw);
+    for (int i = threadIdx.x; i < nr * N; i += NT) {
+      const int rr = i / N, i2 = i - rr * N;
+      Y[(long long)(r0 + rr) * N + i2] = L.tile[rr * NP + i2];
+    }
+    __syncthreads();
+  }
+}
+
+// Y -> forward along i2 on the active rows -> stick row of the plane
+template <int N, int P, typename T>
+__device__ inline void strips_rows_forward(const StripLds<N, T>& L, const GridDev& g,
+                                           const cpx<T>* Y, cpx<T>* row) {
+  using S = Strips<N, T>;
+  constexpr int NT = S::NT, NP = S::NP, RC = S::RC;
+  for (int r0 = 0; r0 < g.nrow; r0 += RC) {
+    const int nr = min(RC, g.nrow - r0);
+    for (int i = threadIdx.x; i < nr * N; i += NT) {
+      const int rr = i / N, i2 = i - rr * N;
+      L.tile[rr * NP + i2] = Y[(long long)(r0 + rr) * N + i2];
+    }
+    __syncthreads();
+    RadixPlan<N, P>::template fft<T, -1, NT, RC>::run(
+        L.tile, nr, 1, [](int f) { return f * NP; }, L.tw);
+    for (int s = threadIdx.x; s < g.nst; s += NT) {
+      const int p = g.stick_i12[s];
+      const int i1 = p / N;
+      const int rr = L.rowidx[i1] - r0;
+      if (rr >= 0 && rr < nr) row[s] = L.tile[rr * NP + (p - i1 * N)];
+    }
+    __syncthreads();
+  }
+}
+
+// columns c0 .. c0 + CC of Y (active rows, zero elsewhere) -> tile [i1][cc]
+// (pitch CP), inverse along i1; `post` maps the outputs of the last pass
+template <int N, int P, typename T, typename Post = NoPost>
+__device__ inline void strips_cols_inverse(const StripLds<N, T>& L, const cpx<T>* Y, int c0,
+                                           Post post = Post()) {
+  using S = Strips<N, T>;
+  constexpr int NT = S::NT, CC = S::CC, CP = S::CP;
+  for (int i = threadIdx.x; i < N * CC; i += NT) {
+    const int i1 = i / CC, cc = i - i1 * CC;
+    const int r = L.rowidx[i1];
+    cpx<T> v = cpx<T>{T(0), T(0)};
+    if (r >= 0) v = Y[(long long)r * N + c0 + cc];
+    L.tile[i1 * CP + cc] = v;
+  }
+  __syncthreads();
+  RadixPlan<N, P>::template fft<T, +1, NT, CC>::run(
+      L.tile, CC, CP, [](int f) { return f; }, L.tw, post);
+}
+
+// multiplies the outputs of the last inverse pass along i1 by V[i1][c0 + cc]
+template <int N, int CP, typename T>
+struct MulPot {
+  const T* V;
+  int c0;
+  __device__ cpx<T> operator()(int a, cpx<T> v) const {
+    const int i1 = a / CP, cc = a - i1 * CP;
+    const T x = V[i1 * N + c0 + cc];
+    return cpx<T>{v.x * x, v.y * x};
+  }
+};
+
+// H_loc (or Delta V_j) on every plane of ncols vectors
+template <int N, int P, typename T>
+__global__ __launch_bounds__((Strips<N, T>::NT)) void k_plane_strips(
+    GridDev g, VecSet<cpx<T>> sticks, const int* slots, int ncols, const T* pot,
+    const T* const* pot_ptr, cpx<T>* scratch) {
+  using S = Strips<N, T>;
+  constexpr int NT = S::NT, CC = S::CC, CP = S::CP;
+  extern __shared__ unsigned char smem_raw[];
+  const StripLds<N, T> L(smem_raw, g);
+  cpx<T>* Y = scratch + (long long)blockIdx.x * g.nrow * N;
+  const long long nplanes = (long long)ncols * N;
+  for (long long q = blockIdx.x; q < nplanes; q += gridDim.x) {
+    const int c = int(q / N), i0 = int(q - (long long)c * N);
+    const int slot = slots[c];
+    cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+    const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+    strips_rows_inverse<N, P, T>(L, g, row, Y);
+    for (int c0 = 0; c0 < N; c0 += CC) {
+      strips_cols_inverse<N, P, T>(L, Y, c0, MulPot<N, CP, T>{V, c0});
+      RadixPlan<N, P>::template fft<T, -1, NT, CC>::run(
+          L.tile, CC, CP, [](int f) { return f; }, L.tw);
+      for (int i = threadIdx.x; i < g.nrow * CC; i += NT) {
+        const int r = i / CC, cc = i - r * CC;
+        Y[(long long)r * N + c0 + cc] = L.tile[g.row_list[r] * CP + cc];
+      }
+      __syncthreads();
+    }
+    strips_rows_forward<N, P, T>(L, g, Y, row);
+  }
+}
+
+// psi(r) planes of ncols vectors on the full grid
+template <int N, int P, typename T>
+__global__ __launch_bounds__((Strips<N, T>::NT)) void k_plane_to_grid_strips(
+    GridDev g, VecSet<const cpx<T>> sticks, VecSet<cpx<T>> grid, const int* slots, int ncols,
+    cpx<T>* scratch) {
+  using S = Strips<N, T>;
+  constexpr int NT = S::NT, CC = S::CC, CP = S::CP;
+  extern __shared__ unsigned char smem_raw[];
+  const StripLds<N, T> L(smem_raw, g);
+  cpx<T>* Y = scratch + (long long)blockIdx.x * g.nrow * N;
+  const long long nplanes = (long long)ncols * N;
+  for (long long q = blockIdx.x; q < nplanes; q += gridDim.x) {
+    const int c = int(q / N), i0 = int(q - (long long)c * N);
+    const int slot = slots[c];
+    const cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+    cpx<T>* dst = grid.base + slot * grid.stride + (long long)i0 * N * N;
+    strips_rows_inverse<N, P, T>(L, g, row, Y);
+    for (int c0 = 0; c0 < N; c0 += CC) {
+      strips_cols_inverse<N, P, T>(L, Y, c0);
+      for (int i = threadIdx.x; i < N * CC; i += NT) {
+        const int i1 = i / CC, cc = i - i1 * CC;
+        dst[i1 * N + c0 + cc] = L.tile[i1 * CP + cc];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Delta n of perturbation j on plane i0 for every (j, i0) of the grid loop,
+// summed over the bands in a fixed order (deterministic, no atomics)
+template <int N, int P>
+__global__ __launch_bounds__((Strips<N, double>::NT)) void k_drho_strips(
+    GridDev g, const z64* sticks, long long sstride, int nband, const int* bands,
+    const z64* psir, double coef, double* drho, int npert, z64* scratch) {
+  using S = Strips<N, double>;
+  constexpr int NT = S::NT, CC = S::CC, CP = S::CP, NCS = S::NCS;
+  constexpr int PERS = (N * CC + NT - 1) / NT;
+  extern __shared__ unsigned char smem_raw[];
+  const StripLds<N, double> L(smem_raw, g);
+  z64* Y = scratch + (long long)blockIdx.x * g.nrow * N;
+  const long long n3 = (long long)N * N * N;
+  const long long nitems = (long long)npert * N;
+  for (long long q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const int j = int(q / N), i0 = int(q - (long long)j * N);
+    double acc[NCS][PERS];
+#pragma unroll
+    for (int cs = 0; cs < NCS; ++cs)
+#pragma unroll
+      for (int k = 0; k < PERS; ++k) acc[cs][k] = 0.0;
+    for (int v = 0; v < nband; ++v) {
+      const z64* row = sticks + ((long long)j * nband + v) * sstride + (long long)i0 * g.nst;
+      strips_rows_inverse<N, P, double>(L, g, row, Y);
+      const z64* pr = psir + (long long)bands[v] * n3 + (long long)i0 * N * N;
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs) {
+        strips_cols_inverse<N, P, double>(L, Y, cs * CC);
+#pragma unroll
+        for (int k = 0; k < PERS; ++k) {
+          const int e = threadIdx.x + k * NT;
+          if (e < N * CC) {
+            const int i1 = e / CC, cc = e - i1 * CC;
+            const z64 a = pr[i1 * N + cs * CC + cc], d = L.tile[i1 * CP + cc];
+            acc[cs][k] += a.x * d.x + a.y * d.y;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    double* out = drho + (long long)j * n3 + (long long)i0 * N * N;
+#pragma unroll
+    for (int cs = 0; cs < NCS; ++cs)
+#pragma unroll
+      for (int k = 0; k < PERS; ++k) {
+        const int e = threadIdx.x + k * NT;
+        if (e < N * CC) {
+          const int i1 = e / CC, cc = e - i1 * CC;
+          out[i1 * N + cs * CC + cc] = coef * acc[cs][k];
+        }
+      }
+  }
+}
+
 // Raises the dynamic LDS limit of one kernel instantiation once per process.
 template <auto K>
 void set_smem(size_t bytes) {
@@ -913,13 +1172,42 @@ int plan_of(const GridDev& g) { return g.plan[sizeof(T) == 4 ? 1 : 0]; }
     }                                                                                 \
   } while (0)
 
+// Every grid, including those whose plane tile exceeds the LDS (z-stick and
+// strip-form kernels).
+#define STH_DISPATCH_ALL(Nval, Pval, ...)                                             \
+  do {                                                                                \
+    if ((Nval) == 144) {                                                              \
+      switch (Pval) {                                                                 \
+        case 0: { constexpr int NN = 144, PP = 0; __VA_ARGS__; } break;              \
+        case 1: { constexpr int NN = 144, PP = 1; __VA_ARGS__; } break;              \
+        default:                                                                      \
+          set_error("unsupported radix plan %d for grid 144", (Pval));                \
+          throw Error(STH_E_INVALID);                                                 \
+      }                                                                               \
+    } else {                                                                          \
+      STH_DISPATCH_NP(Nval, Pval, __VA_ARGS__);                                       \
+    }                                                                                 \
+  } while (0)
+
+// The strip form runs where the tile does not fit, or where it was chosen.
+inline bool use_strips(const GridDev& g, int kind) {
+  return g.N > kTileMaxN || kind == kPlaneStrips;
+}
+
+inline void check_stage(const GridDev& g) {
+  if (!g.stage || g.stage_slots <= 0) {
+    set_error("internal: strip-form plane kernel without scratch planes");
+    throw Error(STH_E_INTERNAL);
+  }
+}
+
 // z-stick kernel form (GridDev::zfft_kind): 0 workgroup form, 1 wave form.
 template <typename T, typename Tin>
 void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> sticks,
                      const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
   const int kind = g.zfft_kind[sizeof(T) == 4 ? 1 : 0];
-  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
+  STH_DISPATCH_ALL(g.N, plan_of<T>(g), {
     if (kind == 0) {
       constexpr int ZS = zsticks<NN, T>();
       dim3 grid((g.nst + ZS - 1) / ZS, ncols);
@@ -936,13 +1224,25 @@ void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> stic
 }
 
 // Plane kernel variants (GridDev::plane_kind): 0 single-pass workgroup form,
-// 1 wave form.
+// 1 wave form, 2 strip form (the only one for grids above kTileMaxN).
 template <typename T>
 void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
                         const T* pot, const T* const* pot_ptr, hipStream_t st) {
   if (ncols <= 0) return;
   dim3 grid(g.N, ncols);
   const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
+  if (use_strips(g, kind)) {
+    check_stage(g);
+    STH_DISPATCH_ALL(g.N, plan_of<T>(g), {
+      using S = Strips<NN, T>;
+      const long long np = (long long)ncols * NN;
+      const dim3 sg((unsigned)std::min<long long>(np, g.stage_slots));
+      hipLaunchKernelGGL((k_plane_strips<NN, PP, T>), sg, dim3(S::NT), S::lds_bytes, st, g,
+                         sticks, slots, ncols, pot, pot_ptr, static_cast<cpx<T>*>(g.stage));
+    });
+    STH_HIP_CHECK(hipGetLastError());
+    return;
+  }
   if (2 * g.nrow > g.N) {   // an alias-free sphere has at most N/2 rows
     set_error("plane kernel: %d active rows exceed N/2 = %d", g.nrow, g.N / 2);
     throw Error(STH_E_INVALID);
@@ -969,7 +1269,7 @@ void launch_zfft_fwd(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<Tout>
                      const double* eps_slot, hipStream_t st) {
   if (ncols <= 0) return;
   const int kind = g.zfft_kind[sizeof(T) == 4 ? 1 : 0];
-  STH_DISPATCH_NP(g.N, plan_of<T>(g), {
+  STH_DISPATCH_ALL(g.N, plan_of<T>(g), {
     if (kind == 0) {
       constexpr int ZS = zsticks<NN, T>();
       dim3 grid((g.nst + ZS - 1) / ZS, ncols);
@@ -989,6 +1289,18 @@ template <typename T>
 void launch_plane_to_grid(const GridDev& g, VecSet<const cpx<T>> sticks, VecSet<cpx<T>> grid_out,
                           const int* slots, int ncols, hipStream_t st) {
   if (ncols <= 0) return;
+  if (use_strips(g, g.plane_kind[sizeof(T) == 4 ? 1 : 0])) {
+    check_stage(g);
+    STH_DISPATCH_ALL(g.N, plan_of<T>(g), {
+      using S = Strips<NN, T>;
+      const long long np = (long long)ncols * NN;
+      const dim3 sg((unsigned)std::min<long long>(np, g.stage_slots));
+      hipLaunchKernelGGL((k_plane_to_grid_strips<NN, PP, T>), sg, dim3(S::NT), S::lds_bytes, st,
+                         g, sticks, grid_out, slots, ncols, static_cast<cpx<T>*>(g.stage));
+    });
+    STH_HIP_CHECK(hipGetLastError());
+    return;
+  }
   dim3 grid(g.N, ncols);
   STH_DISPATCH_NP(g.N, plan_of<T>(g), {
     constexpr size_t sm = PlaneLds<NN, T>::bytes(false);
@@ -1003,6 +1315,19 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
                  const int* bands, const z64* psir, int npert, double coef, double* drho,
                  hipStream_t st) {
   if (npert <= 0) return;
+  if (use_strips(g, g.plane_kind[0])) {
+    check_stage(g);
+    STH_DISPATCH_ALL(g.N, plan_of<double>(g), {
+      using S = Strips<NN, double>;
+      const long long ni = (long long)npert * NN;
+      const dim3 sg((unsigned)std::min<long long>(ni, g.stage_slots));
+      hipLaunchKernelGGL((k_drho_strips<NN, PP>), sg, dim3(S::NT), S::lds_bytes, st, g, sticks,
+                         stick_stride, nband, bands, psir, coef, drho, npert,
+                         static_cast<z64*>(g.stage));
+    });
+    STH_HIP_CHECK(hipGetLastError());
+    return;
+  }
   dim3 grid(g.N, npert);
   STH_DISPATCH_NP(g.N, plan_of<double>(g), {
     constexpr size_t sm = PlaneLds<NN, double>::bytes(false);
@@ -1017,6 +1342,13 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // attribute call happens while a stream is being captured into a graph.
 void prepare_fft_kernels(int N) {
   for (int p = 0; p < kRadixPlans; ++p) {
+    STH_DISPATCH_ALL(N, p, {
+      set_smem<k_plane_strips<NN, PP, double>>(Strips<NN, double>::lds_bytes);
+      set_smem<k_plane_strips<NN, PP, float>>(Strips<NN, float>::lds_bytes);
+      set_smem<k_plane_to_grid_strips<NN, PP, double>>(Strips<NN, double>::lds_bytes);
+      set_smem<k_drho_strips<NN, PP>>(Strips<NN, double>::lds_bytes);
+    });
+    if (N > kTileMaxN) continue;
     STH_DISPATCH_NP(N, p, {
       set_smem<k_plane_fused<NN, PP, double>>(fused_lds_bytes<NN, double>());
       set_smem<k_plane_fused<NN, PP, float>>(fused_lds_bytes<NN, float>());

@@ -18,13 +18,16 @@ struct GridDev {
   const int* stick_i12 = nullptr;  // [nst] i1 * N + i2 of each stick
   const int* row_list = nullptr;   // [nrow] active i1 rows
   const unsigned long long* rowbits = nullptr;  // [N][2] bit i2 set: (i1, i2) holds a stick
+                                                // (filled for N <= 128, the tile forms' grids)
   unsigned long long rowmask[3] = {0, 0, 0};  // bit i1: row i1 is active (N <= 192)
   const double* kin = nullptr;     // [npw] |G|^2 / 2
   const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
   const z32* tw32 = nullptr;       // [N] same, rounded to FP32
   int plan[2] = {0, 0};            // radix plan of the FFT kernels: [0] FP64, [1] FP32
   int plane_kind[2] = {0, 0};      // plane kernel form (0..kPlaneKinds-1): [0] FP64, [1] FP32
-  int zfft_kind[2] = {0, 0};       // z-stick kernel form (0..kPlaneKinds-1): [0] FP64, [1] FP32
+  int zfft_kind[2] = {0, 0};       // z-stick kernel form (0..kZfftKinds-1): [0] FP64, [1] FP32
+  void* stage = nullptr;           // strip form: [stage_slots][nrow][N] complex scratch planes
+  int stage_slots = 0;             //   (sized for FP64; one per resident workgroup)
 };
 
 // A set of vectors addressed through a slot list: vector for list entry c is
@@ -64,7 +67,11 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // LDS attributes of the plane kernels of grid N (call before any graph capture)
 void prepare_fft_kernels(int N);
 constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
-constexpr int kPlaneKinds = 2;       // plane / z-stick kernels: workgroup form, wave form
+constexpr int kPlaneKinds = 3;       // plane kernels: workgroup form, wave form, strip form
+constexpr int kZfftKinds = 2;        // z-stick kernels: workgroup form, wave form
+constexpr int kPlaneStrips = 2;      // plane_kind of the strip form
+constexpr int kTileMaxN = 96;        // largest grid whose N x (N + 1) FP64 plane tile fits in LDS
+constexpr int kStageSlots = 512;     // strip-form workgroups in flight (two per CU)
 
 // ---- dense contractions on MFMA (FP64) ----
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)

@@ -82,7 +82,8 @@ void Context::autotune(System& s) {
     bool ok = c.kchunk >= s.kchunk;
     for (int k = 0; k < 2; ++k)
       ok = ok && c.plan[k] >= 0 && c.plan[k] < kRadixPlansHost && c.kind[k] >= 0 &&
-           c.kind[k] < kPlaneKinds && c.zkind[k] >= 0 && c.zkind[k] < kPlaneKinds;
+           c.kind[k] < kPlaneKinds && c.zkind[k] >= 0 && c.zkind[k] < kZfftKinds &&
+           (s.N <= kTileMaxN || c.kind[k] == kPlaneStrips);
     if (ok) {
       for (int k = 0; k < 2; ++k) {
         s.g.plan[k] = c.plan[k];
@@ -118,12 +119,14 @@ void Context::autotune(System& s) {
   VecSet<z64> st64{s.d_sticks.as<z64>(), (long long)N * s.nst};
   VecSet<z32> st32{reinterpret_cast<z32*>(s.d_sticks.as<z64>()), (long long)N * s.nst};
   // FFT stages of H psi for every (radix plan, plane kernel form, z-stick kernel
-  // form), per precision
+  // form), per precision; grids whose plane tile exceeds the LDS have the strip
+  // form only
+  const int kind0 = s.N > kTileMaxN ? kPlaneStrips : 0;
   for (int k = 0; k < 2; ++k) {
     double bt = 1e300;
-    int bp = 0, bkind = 0, bz = 0;
-    for (int zk = 0; zk < kPlaneKinds; ++zk) {
-      for (int kind = 0; kind < kPlaneKinds; ++kind) {
+    int bp = 0, bkind = kind0, bz = 0;
+    for (int zk = 0; zk < kZfftKinds; ++zk) {
+      for (int kind = kind0; kind < kPlaneKinds; ++kind) {
         for (int p = 0; p < kRadixPlansHost; ++p) {
           s.g.plan[k] = p;
           s.g.plane_kind[k] = kind;
@@ -141,7 +144,7 @@ void Context::autotune(System& s) {
                                           ZF_PLAIN, {nullptr, 0}, nullptr, st_);
             }
           });
-          s.tune_ms[8 * k + 4 * zk + 2 * kind + p] = ms;
+          s.tune_ms[12 * k + 6 * zk + 2 * kind + p] = ms;
           if (ms < bt) {
             bt = ms;
             bp = p;
@@ -170,7 +173,7 @@ void Context::autotune(System& s) {
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[16 + ncand++] = ms;
+    s.tune_ms[24 + ncand++] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;
@@ -204,7 +207,7 @@ void Context::system_info(int id, sth_system_info* info) {
   info->zfft_kernel_fp64 = s.g.zfft_kind[0];
   info->zfft_kernel_fp32 = s.g.zfft_kind[1];
   info->gemm_kchunk = s.kchunk;
-  for (int i = 0; i < 24; ++i) info->tune_ms[i] = s.tune_ms[i];
+  for (int i = 0; i < 32; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
 }
 

@@ -13,7 +13,10 @@
 // eigenproblems run on the device Jacobi solver.  A block of nbands + 8
 // vectors is iterated; the lowest nbands must meet the tolerance.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <random>
@@ -146,8 +149,8 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
     set_error("valence: invalid system description");
     throw Error(STH_E_INVALID);
   }
-  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96) {
-    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96)", d.n);
+  if (d.n != 24 && d.n != 48 && d.n != 72 && d.n != 96 && d.n != 144) {
+    set_error("unsupported grid n=%d (supported: 24, 48, 72, 96, 144)", d.n);
     throw Error(STH_E_INVALID);
   }
   const int guard = 8;
@@ -157,6 +160,10 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
     throw Error(STH_E_INVALID);
   }
   if (maxit <= 0) maxit = 500;
+  // STH_VERBOSE=1: one progress line per iteration on stderr (long eigensolves)
+  const char* ve = std::getenv("STH_VERBOSE");
+  const bool verbose = ve && std::atoi(ve) != 0;
+  const auto t_start = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> glk(gpu_mu_);
   STH_HIP_CHECK(hipSetDevice(device_));
   System s;
@@ -216,6 +223,10 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
     STH_HIP_CHECK(hipStreamSynchronize(st_));
     res = 0.0;
     for (int i = 0; i < nbands; ++i) res = std::max(res, std::sqrt(rn[i]));
+    if (verbose)
+      std::fprintf(stderr, "valence: iteration %d, max residual %.3e, %.1f s\n", it, res,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
+                       .count());
     if (!(res == res)) {
       set_error("valence: non-finite residual");
       throw Error(STH_E_INTERNAL);

@@ -1,0 +1,116 @@
+"""GPU parity on the grids of the served 216-atom system and the 512-atom share.
+
+96^3 (216 atoms, 54,435 plane waves, 864 KB projectors): the plane tile still
+fits in LDS.  144^3 (512 atoms, 187,511 plane waves, 2048 KB projectors): the
+FP64 plane tile (334 KB) exceeds the LDS, so only the strip form of the plane
+kernels runs there.  Calls go through the C-ABI.
+
+* H.psi against the oracle's FFT route, 1e-12 relative, on both grids.
+* 144^3: Sternheimer solves for the lowest band and two perturbations, FP64 at
+  tolerance 1e-12 (Delta psi and Delta n within 1e-10) and STH_MIXED_BF16 at
+  1e-8 (Delta psi within 1e-6), against the oracle's PCG solutions cached by
+  tests/golden/make_response_cache.py from the oracle valence states of
+  tests/golden/make_valence_cache.py (skipped when the caches are missing).
+"""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+CACHE = os.path.join(ROOT, "tests", "_cache")
+
+
+@pytest.fixture(scope="module")
+def sth():
+    import paper_2203_05623_amd as P
+    ctx = P.sth_create(device=0, max_slots=64)
+    yield P, ctx
+    P.sth_destroy(ctx)
+
+
+@functools.lru_cache(maxsize=2)
+def _system(name):
+    return oracle.build_system(name)
+
+
+def _orthonormal_rows(npw, nv, seed):
+    """nv orthonormal vectors (any orthonormal set serves H.psi, which ignores them)."""
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.standard_normal((npw, nv)) + 1j * rng.standard_normal((npw, nv)))
+    return np.ascontiguousarray(q.T)
+
+
+@pytest.mark.parametrize("name", ["cfg4c", "cfg5"])
+def test_apply_h_large_grid(sth, name):
+    P, ctx = sth
+    cfg = workloads.get_config(name)
+    s = _system(name)
+    psi = _orthonormal_rows(s.npw, 4, 3)
+    sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi,
+                           np.arange(4.0))
+    try:
+        info = P.sth_system_info_get(ctx, sid)
+        print(name, {k: v for k, v in info.items() if k != "tune_ms"})
+        if cfg.N > 96:
+            assert info["plane_kernel_fp64"] == 2 and info["plane_kernel_fp32"] == 2
+        rng = np.random.default_rng(31)
+        c = rng.standard_normal((3, s.npw)) + 1j * rng.standard_normal((3, s.npw))
+        got = P.sth_apply_h(ctx, sid, c)
+        ref = oracle.apply_H(s, c)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"{name} (N={cfg.N}) H.psi rel err {err:.2e}")
+        assert err < 1e-12
+    finally:
+        P.sth_release_system(ctx, sid)
+
+
+def test_solves_144_lowest_band(sth):
+    P, ctx = sth
+    cfg = workloads.get_config("cfg5")
+    vpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_valence.npz")
+    rpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_response.npz")
+    if not (os.path.exists(vpath) and os.path.exists(rpath)):
+        pytest.skip("oracle caches missing: run tests/golden/make_valence_cache.py cfg5 1e-11 1 "
+                    "and tests/golden/make_response_cache.py cfg5 1")
+    d, r = np.load(vpath), np.load(rpath)
+    s = _system("cfg5")
+    psi, eps = np.ascontiguousarray(d["psi"][:1]), d["eps"][:1]
+    ref_x, ref_dn = r["dpsi"], r["drho"]
+    npert = ref_x.shape[0]
+    dv = workloads.dv_block(cfg, range(npert))
+    sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+    try:
+        t = P.sth_submit_solves(ctx, sid, dv, np.array([0]), tol=1e-12, want_dpsi=True)
+        assert P.sth_wait(ctx, t, 120.0)
+        x = np.empty((npert, 1, s.npw), np.complex128)
+        P.sth_fetch_dpsi(ctx, t, x)
+        dn = np.empty((npert, cfg.N, cfg.N, cfg.N))
+        P.sth_fetch_drho(ctx, t, dn)
+        iters, resid, status, _ = P.sth_fetch_stats(ctx, t, npert)
+        P.sth_release_ticket(ctx, t)
+        assert np.all(status == 0)
+        e_x = max(np.linalg.norm(x[j, 0] - ref_x[j]) / np.linalg.norm(ref_x[j])
+                  for j in range(npert))
+        e_dn = np.abs(dn - ref_dn).max() / np.abs(ref_dn).max()
+        print(f"144^3 FP64: iterations {iters}, dpsi {e_x:.2e}, dn {e_dn:.2e}")
+        assert e_x < 1e-10 and e_dn < 1e-10
+        t = P.sth_submit_solves(ctx, sid, dv, np.array([0]), tol=1e-8,
+                                precision=P.STH_MIXED_BF16, want_dpsi=True)
+        assert P.sth_wait(ctx, t, 120.0)
+        P.sth_fetch_dpsi(ctx, t, x)
+        iters, resid, status, _ = P.sth_fetch_stats(ctx, t, npert)
+        P.sth_release_ticket(ctx, t)
+        assert np.all(status == 0) and resid.max() <= 1e-8
+        e_x = max(np.linalg.norm(x[j, 0] - ref_x[j]) / np.linalg.norm(ref_x[j])
+                  for j in range(npert))
+        print(f"144^3 mixed-bf16: iterations {iters}, dpsi {e_x:.2e}")
+        assert e_x < 1e-6
+    finally:
+        P.sth_release_system(ctx, sid)

@@ -2,11 +2,14 @@
 
 The autotuner keeps the fastest (radix plan, plane kernel form, z-stick kernel
 form) per precision, so a normal run exercises only one of them.  Here every radix
-plan and every kernel form of both stages is forced through the tuning cache
+plan and every kernel form of both stages (plane: workgroup, wave and strip forms;
+z-sticks: workgroup and wave forms) is forced through the tuning cache
 (STH_TUNE_CACHE) in FP64 and in FP32 and checked against the oracle: H.psi in FP64
 (1e-12 relative) and mixed-precision solves, whose inner operator uses the FP32
-variant (1e-6 relative on Delta psi at true residual 1e-8).  Config 1 (24^3,
-plans (8, 3) and (4, 6)) and the benchmark system (72^3, plans (8, 9) and (9, 8)).
+variant (1e-6 relative on Delta psi at true residual 1e-8).  On config 1 also FP64
+solves at 1e-12 with their Delta n (1e-10), which run psi_v(r) and Delta n
+through the FP64 form.  Config 1 (24^3, plans (8, 3) and (4, 6)) and the
+benchmark system (72^3, plans (8, 9) and (9, 8)).
 """
 import os
 
@@ -19,15 +22,15 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
-VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1)]
+VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1, 2)]
 
 
 def _force(path, info, M, plan, kind):
     key = (f"gfx950 N={info['N']} npw={info['npw']} nst={info['nsticks']} M={M} "
            f"slots={info['nslots']}")
     with open(path, "a") as f:
-        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "zkind64": {kind}, '
-                f'"plan32": {plan}, "kind32": {kind}, "zkind32": {1 - kind}, '
+        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "zkind64": {kind % 2}, '
+                f'"plan32": {plan}, "kind32": {kind}, "zkind32": {1 - kind % 2}, '
                 f'"kchunk": {info["gemm_kchunk"]}}}\n')
 
 
@@ -46,9 +49,9 @@ def _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
         got = P.sth_system_info_get(ctx, sid)
         assert got["tuned_from_cache"] == 1
         assert (got["fft_plan_fp64"], got["plane_kernel_fp64"], got["zfft_kernel_fp64"]) == \
-            (plan, kind, kind)
+            (plan, kind, kind % 2)
         assert (got["fft_plan_fp32"], got["plane_kernel_fp32"], got["zfft_kernel_fp32"]) == \
-            (plan, kind, 1 - kind)
+            (plan, kind, 1 - kind % 2)
         yield plan, kind, sid
         P.sth_release_system(ctx, sid)
     monkeypatch.delenv("STH_TUNE_CACHE")
@@ -67,6 +70,7 @@ def test_variants_cfg1(cfg1_system, cfg1_dense, monkeypatch, tmp_path):
     dv = workloads.dv_block(cfg, range(2))
     ref_x = np.array([[oracle.solve_lu(H, psi, eps[v], oracle.rhs(s, psi, v, dv[j]))
                        for v in range(nv)] for j in range(2)])
+    ref_dn = np.stack([oracle.drho(s, psi, ref_x[j]) for j in range(2)])
     ctx = P.sth_create(device=0, max_slots=64)
     try:
         for plan, kind, sid in _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
@@ -80,9 +84,20 @@ def test_variants_cfg1(cfg1_system, cfg1_dense, monkeypatch, tmp_path):
             P.sth_release_ticket(ctx, t)
             e_x = max(np.linalg.norm(x[j, v] - ref_x[j, v]) / np.linalg.norm(ref_x[j, v])
                       for j in range(2) for v in range(nv))
-            print(f"cfg1 plan {plan} kind {kind}: H.psi {e_h:.2e}, mixed dpsi {e_x:.2e}")
+            t = P.sth_submit_solves(ctx, sid, dv, np.arange(nv), tol=1e-12, want_dpsi=True)
+            assert P.sth_wait(ctx, t, 120.0)
+            P.sth_fetch_dpsi(ctx, t, x)
+            dn = np.empty((2, cfg.N, cfg.N, cfg.N))
+            P.sth_fetch_drho(ctx, t, dn)
+            P.sth_release_ticket(ctx, t)
+            e_x64 = max(np.linalg.norm(x[j, v] - ref_x[j, v]) / np.linalg.norm(ref_x[j, v])
+                        for j in range(2) for v in range(nv))
+            e_dn = np.abs(dn - ref_dn).max() / np.abs(ref_dn).max()
+            print(f"cfg1 plan {plan} kind {kind}: H.psi {e_h:.2e}, mixed dpsi {e_x:.2e}, "
+                  f"FP64 dpsi {e_x64:.2e}, dn {e_dn:.2e}")
             assert e_h < 1e-12
             assert e_x < 1e-6
+            assert e_x64 < 1e-10 and e_dn < 1e-10
     finally:
         P.sth_destroy(ctx)
 
