@@ -143,9 +143,13 @@ def served(args):
         if arrivals[k] > now:
             time.sleep(arrivals[k] - now)
         live.append((k, names[choice[k]], submit(names[choice[k]])))
+        if (k + 1) % 10 == 0:
+            print(f"submitted {k + 1} of {nreq + warm} requests", file=sys.stderr, flush=True)
     req_lat, solve_lat, done_solves = [], [], 0
     for k, name, t in live:
         P.sth_wait(ctx, t, 3600.0)
+        if (k + 1) % 10 == 0:
+            print(f"request {k + 1} done", file=sys.stderr, flush=True)
         info = P.sth_poll(ctx, t)
         if k >= warm:
             n = info["n_total"]
@@ -191,7 +195,7 @@ def main():
                          "compute them on the device and save them there")
     ap.add_argument("--served", action="store_true",
                     help="served mode: Poisson request stream over several systems")
-    ap.add_argument("--served-systems", default="cfg4a,cfg4b")
+    ap.add_argument("--served-systems", default="cfg4a,cfg4b,cfg4c")
     ap.add_argument("--served-requests", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -921,6 +921,12 @@ struct Strips {
   static constexpr size_t lds_bytes = tile_bytes + N * sizeof(cpx<T>) + N * sizeof(int);
 };
 
+// rows per strip when nrow rows are split into the fewest strips of <= rc rows
+__device__ inline int strip_rows_balanced(int nrow, int rc) {
+  const int ns = (nrow + rc - 1) / rc;
+  return (nrow + ns - 1) / ns;
+}
+
 // LDS of a strip-form workgroup: strip tile, twiddles, row index (i1 -> position
 // in the active-row list, -1 for an empty row).
 template <int N, typename T>
@@ -947,8 +953,9 @@ __device__ inline void strips_rows_inverse(const StripLds<N, T>& L, const GridDe
                                            const cpx<T>* row, cpx<T>* Y) {
   using S = Strips<N, T>;
   constexpr int NT = S::NT, NP = S::NP, RC = S::RC;
-  for (int r0 = 0; r0 < g.nrow; r0 += RC) {
-    const int nr = min(RC, g.nrow - r0);
+  const int rs = strip_rows_balanced(g.nrow, RC);
+  for (int r0 = 0; r0 < g.nrow; r0 += rs) {
+    const int nr = min(rs, g.nrow - r0);
     for (int i = threadIdx.x; i < nr * NP; i += NT) L.tile[i] = cpx<T>{T(0), T(0)};
     __syncthreads();
     for (int s = threadIdx.x; s < g.nst; s += NT) {
@@ -974,8 +981,9 @@ __device__ inline void strips_rows_forward(const StripLds<N, T>& L, const GridDe
                                            const cpx<T>* Y, cpx<T>* row) {
   using S = Strips<N, T>;
   constexpr int NT = S::NT, NP = S::NP, RC = S::RC;
-  for (int r0 = 0; r0 < g.nrow; r0 += RC) {
-    const int nr = min(RC, g.nrow - r0);
+  const int rs = strip_rows_balanced(g.nrow, RC);
+  for (int r0 = 0; r0 < g.nrow; r0 += rs) {
+    const int nr = min(rs, g.nrow - r0);
     for (int i = threadIdx.x; i < nr * N; i += NT) {
       const int rr = i / N, i2 = i - rr * N;
       L.tile[rr * NP + i2] = Y[(long long)(r0 + rr) * N + i2];

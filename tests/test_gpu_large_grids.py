@@ -11,6 +11,9 @@ kernels runs there.  Calls go through the C-ABI.
   1e-8 (Delta psi within 1e-6), against the oracle's PCG solutions cached by
   tests/golden/make_response_cache.py from the oracle valence states of
   tests/golden/make_valence_cache.py (skipped when the caches are missing).
+  The oracle's LOBPCG is run to residual 3e-9 at this size (it stalls near
+  2e-9); both sides take the same psi_0, and the shifted operator of the HIP
+  path differs from the projected one only at second order in that residual.
 """
 import functools
 import os
@@ -58,7 +61,7 @@ def test_apply_h_large_grid(sth, name):
     try:
         info = P.sth_system_info_get(ctx, sid)
         print(name, {k: v for k, v in info.items() if k != "tune_ms"})
-        if cfg.N > 96:
+        if cfg.N > 96:   # only the strip form fits
             assert info["plane_kernel_fp64"] == 2 and info["plane_kernel_fp32"] == 2
         rng = np.random.default_rng(31)
         c = rng.standard_normal((3, s.npw)) + 1j * rng.standard_normal((3, s.npw))
@@ -77,7 +80,7 @@ def test_solves_144_lowest_band(sth):
     vpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_valence.npz")
     rpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_response.npz")
     if not (os.path.exists(vpath) and os.path.exists(rpath)):
-        pytest.skip("oracle caches missing: run tests/golden/make_valence_cache.py cfg5 1e-11 1 "
+        pytest.skip("oracle caches missing: run tests/golden/make_valence_cache.py cfg5 3e-9 1 "
                     "and tests/golden/make_response_cache.py cfg5 1")
     d, r = np.load(vpath), np.load(rpath)
     s = _system("cfg5")
