@@ -71,7 +71,7 @@ constexpr int kPlaneKinds = 3;       // plane kernels: workgroup form, wave form
 constexpr int kZfftKinds = 2;        // z-stick kernels: workgroup form, wave form
 constexpr int kPlaneStrips = 2;      // plane_kind of the strip form
 constexpr int kTileMaxN = 96;        // largest grid whose N x (N + 1) FP64 plane tile fits in LDS
-constexpr int kStageSlots = 512;     // strip-form workgroups in flight (two per CU)
+constexpr int kStageSlots = 1024;    // strip-form persistent workgroups (up to four per CU)
 
 // ---- dense contractions on MFMA (FP64) ----
 // part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)
