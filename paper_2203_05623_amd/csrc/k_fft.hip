@@ -237,18 +237,16 @@ struct RowBits {
 
 // The stick row of plane i0 into the tile (coalesced reads; cells without a
 // stick keep stale values, the first pass reads them as zero), and back.
-template <int N, int NT, typename T>
+template <int N, int NT, typename T, int NP = N + 1>
 __device__ inline void sticks_to_tile(cpx<T>* tile, const GridDev& g, const cpx<T>* row) {
-  constexpr int NP = N + 1;
   for (int s = threadIdx.x; s < g.nst; s += NT) {
     const int p = g.stick_i12[s];
     const int i1 = p / N;
     tile[i1 * NP + (p - i1 * N)] = row[s];
   }
 }
-template <int N, int NT, typename T>
+template <int N, int NT, typename T, int NP = N + 1>
 __device__ inline void tile_to_sticks(const cpx<T>* tile, const GridDev& g, cpx<T>* row) {
-  constexpr int NP = N + 1;
   for (int s = threadIdx.x; s < g.nst; s += NT) {
     const int p = g.stick_i12[s];
     const int i1 = p / N;
@@ -276,22 +274,27 @@ __device__ inline bool row_active(const GridDev& g, int i1) {
 //   B1h  along i1, pass 1^H; outputs kept for the active rows only
 //   A2h  along i2, pass 2^H on the active rows
 //   A1h  along i2, pass 1^H; outputs scattered straight to the stick row
-// Passes along i2 give consecutive lanes consecutive rows (odd LDS pitch), passes
-// along i1 consecutive columns: no bank conflicts either way.
+// Passes along i2 give consecutive lanes consecutive butterflies of one row,
+// passes along i1 consecutive columns.
 template <int N, int P>
 constexpr int fused_threads() {
   return pthreads<N, P>();
 }
+// LDS row pitch of the single-pass tile (elements)
+template <int N, typename T>
+constexpr int fused_pitch() {
+  return N + 1;
+}
 template <int N, typename T>
 constexpr size_t fused_lds_bytes() {
-  return size_t(N) * (N + 1) * sizeof(cpx<T>);
+  return size_t(N) * fused_pitch<N, T>() * sizeof(cpx<T>);
 }
 
 template <int N, int P, typename T>
 __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
     GridDev g, VecSet<cpx<T>> sticks, const int* slots, const T* pot, const T* const* pot_ptr) {
   constexpr int NT = fused_threads<N, P>();
-  constexpr int NP = N + 1;
+  constexpr int NP = fused_pitch<N, T>();
   constexpr int R1 = RadixPlan<N, P>::radix(0), R2 = RadixPlan<N, P>::radix(1);
   static_assert(R1 * R2 == N, "two-pass plan");
   constexpr int M1 = N / R1, M2 = N / R2;
@@ -306,7 +309,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
   const cpx<T>* tw = twiddles<T>(g);
   const int nrow = g.nrow;
 
-  sticks_to_tile<N, NT, T>(tile, g, row);
+  sticks_to_tile<N, NT, T, NP>(tile, g, row);
   __syncthreads();
   {   // A1: loads, barrier, stores (in place along the row)
     constexpr int TA = (N / 2 * M1 + NT - 1) / NT;   // at most N/2 active rows
@@ -470,7 +473,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
     }
   }
   __syncthreads();
-  tile_to_sticks<N, NT, T>(tile, g, row);
+  tile_to_sticks<N, NT, T, NP>(tile, g, row);
 }
 
 // H_loc on one plane, wave form: the passes of k_plane_fused, with every
