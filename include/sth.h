@@ -225,6 +225,26 @@ sth_status sth_chi0_block(sth_ctx* ctx, uint64_t ticket, double* M, double* S, d
 /* Frees a finished ticket's device results. */
 sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket);
 
+/* The npdep lowest (most negative) eigenpairs of chi_bar0 = v^{1/2} chi0 v^{1/2}
+ * of a resident system, v^{1/2}(G) = sqrt(4 pi) / |G| (paper, Section 3: the
+ * projective dielectric eigendecomposition, whose chi0 products come from the
+ * Sternheimer solves).  Block Davidson on real grid functions band-limited to
+ * the density sphere |m|^2 <= 4 max|m|^2 of the system's sphere, without G = 0,
+ * with the inner product (Omega/n^3) sum_r: each chi_bar0 product runs the
+ * Sternheimer solves of every valence band on this context's solve server
+ * (true relative residual solve_tol, `precision` STH_FP64 / STH_MIXED /
+ * STH_MIXED_BF16); Rayleigh-Ritz in FP64 on the device; the residuals of the
+ * unconverged pairs extend the basis (at most nmax >= 2 npdep vectors, then a
+ * restart from the Ritz vectors).  Stops when every residual
+ * ||chi_bar0 y - lambda y|| <= tol, after maxit iterations, or when no new
+ * direction remains.  eig_out [npdep] ascending, host memory; vec_out (may be
+ * NULL) real [npdep][n^3] orthonormal eigenvectors (C order) in `vec_ptr_kind`
+ * memory; *iters and *max_resid (may be NULL) report the run (max_resid > tol:
+ * not converged).  Grids up to 96.  STH_E_INVALID for bad arguments. */
+sth_status sth_pdep(sth_ctx* ctx, int32_t system_id, int npdep, int nmax, double tol, int maxit,
+                    double solve_tol, int precision, double* eig_out, double* vec_out,
+                    int vec_ptr_kind, void* stream, int* iters, double* max_resid);
+
 /* Kernel timing of the solve server, for measurement: with enable != 0 the
  * library records HIP events (on its own stream) around every kernel launch
  * of the CG iterations, grouped by phase:

@@ -25,7 +25,7 @@ SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
            "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
            "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
-           "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_last_error"]
+           "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_pdep", "sth_last_error"]
 PHASES = ["zfft_inv", "plane", "zfft_fwd", "gemm_ah_b", "reduce", "gemm_a_c", "cg", "rhs_retire"]
 
 
@@ -94,6 +94,8 @@ def load():
         "sth_profile": [vp, C.c_int],
         "sth_profile_read": [vp, vp, vp, vp, vp],
         "sth_system_info_get": [vp, i32, C.POINTER(sth_system_info)],
+        "sth_pdep": [vp, i32, C.c_int, C.c_int, dbl, C.c_int, dbl, C.c_int, vp, vp, C.c_int, vp,
+                     C.POINTER(C.c_int), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -296,6 +298,20 @@ def sth_chi0_block(ctx, ticket, npert):
 
 def sth_release_ticket(ctx, ticket):
     _check(lib().sth_release_ticket(ctx, ticket))
+
+
+def sth_pdep(ctx, system_id, n, npdep, nmax=0, tol=1e-6, maxit=100, solve_tol=1e-10,
+             precision=STH_FP64, want_vectors=True):
+    """(eigenvalues [npdep], eigenvectors [npdep, n, n, n] or None, iterations, max residual);
+    n is the system's grid size (shape of the vectors); nmax 0 means 4 npdep."""
+    eig = np.empty(npdep)
+    vec = np.empty((npdep, n, n, n)) if want_vectors else None
+    its = C.c_int()
+    res = C.c_double()
+    _check(lib().sth_pdep(ctx, system_id, npdep, nmax or 4 * npdep, tol, maxit, solve_tol,
+                          precision, eig.ctypes.data, vec.ctypes.data if want_vectors else None,
+                          STH_PTR_HOST, None, C.byref(its), C.byref(res)))
+    return eig, vec, its.value, res.value
 
 
 def sth_profile(ctx, enable=True):

@@ -173,6 +173,16 @@ sth_status sth_chi0_block(sth_ctx* ctx, uint64_t ticket, double* M, double* S, d
   return guard([&] { ctx_of(ctx)->chi0_block(ticket, M, S, lambda); });
 }
 
+sth_status sth_pdep(sth_ctx* ctx, int32_t system_id, int npdep, int nmax, double tol, int maxit,
+                    double solve_tol, int precision, double* eig_out, double* vec_out,
+                    int vec_ptr_kind, void* stream, int* iters, double* max_resid) {
+  return guard([&] {
+    need(eig_out != nullptr, "eig_out");
+    ctx_of(ctx)->pdep(system_id, npdep, nmax, tol, maxit, solve_tol, precision, eig_out, vec_out,
+                      vec_ptr_kind, static_cast<hipStream_t>(stream), iters, max_resid);
+  });
+}
+
 sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket) {
   return guard([&] { ctx_of(ctx)->release_ticket(ticket); });
 }

@@ -99,6 +99,10 @@ DevMem upload(Budget* b, const std::vector<T>& v, hipStream_t st) {
   return m;
 }
 
+int imod(int a, int n) { return ((a % n) + n) % n; }
+
+}  // namespace
+
 // Copies `bytes` from caller memory (host or device) into device memory.
 void copy_in(void* dst, const void* src, size_t bytes, int ptr_kind, hipStream_t st) {
   if (bytes == 0) return;
@@ -122,10 +126,6 @@ void check_ptr_kind(int k) {
     throw Error(STH_E_INVALID);
   }
 }
-
-int imod(int a, int n) { return ((a % n) + n) % n; }
-
-}  // namespace
 
 // ------------------------------------------------------------------ context
 Context::Context(const sth_config& cfg)
@@ -323,6 +323,11 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.M = nv + d.nproj;
   s.L = d.L;
   s.omega = d.L * d.L * d.L;
+  s.m2 = 0;
+  for (int k = 0; k < d.npw; ++k) {
+    const int* m = d.miller + 3 * k;
+    s.m2 = std::max(s.m2, m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  }
   s.fs = d.spin_factor;
   StickBuild sb = build_sticks(d.miller, d.npw, d.n, d.L);
   s.nst = int(sb.stick_off.size()) - 1;

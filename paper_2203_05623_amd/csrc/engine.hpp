@@ -101,6 +101,12 @@ void gen_eig_device(Budget* b, const std::vector<double>& M, const std::vector<d
 
 struct Request;
 
+// Copies between caller memory (STH_PTR_HOST or STH_PTR_DEVICE) and device memory,
+// stream-ordered on st; check_ptr_kind rejects any other kind (STH_E_INVALID).
+void copy_in(void* dst, const void* src, size_t bytes, int ptr_kind, hipStream_t st);
+void copy_out(void* dst, const void* src, size_t bytes, int ptr_kind, hipStream_t st);
+void check_ptr_kind(int k);
+
 // Host-side stick maps of a sphere (see build_sticks).
 struct StickBuild {
   std::vector<int> perm;        // caller index -> internal index
@@ -118,6 +124,7 @@ struct SlotHost {
 struct System {
   int id = 0;
   int N = 0, npw = 0, nst = 0, nrow = 0, nv = 0, nproj = 0, M = 0;
+  int m2 = 0;          // largest |m|^2 on the sphere (density sphere: |m|^2 <= 4 m2)
   double L = 0.0, omega = 0.0, fs = 2.0, alpha_pv = 0.0;
   GridDev g;
   DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
@@ -217,6 +224,9 @@ class Context {
   void chi0_block(uint64_t t, double* M, double* S, double* lam);
   void release_ticket(uint64_t t);
   void system_info(int id, sth_system_info* info);
+  void pdep(int id, int npdep, int nmax, double tol, int maxit, double solve_tol, int precision,
+            double* eig_out, double* vec_out, int ptr_kind, hipStream_t user, int* iters,
+            double* max_resid);
 
  private:
   void autotune(System& s);

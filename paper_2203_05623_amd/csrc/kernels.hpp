@@ -194,4 +194,28 @@ void launch_resid_precond(const GridDev& g, const z64* X, const z64* HX, const d
 void launch_cols_to_rows(const z64* U, int ldu, int m0, int nm, int col0, int nc,
                          const double* scale, z64* C, hipStream_t st);
 
+// ---- dielectric eigensolver (real grid functions, stride ld between vectors) ----
+// LDS attributes of the full-grid FFT kernels of grid N (N <= kTileMaxN)
+void prepare_grid_fft(int N);
+// in-place full-grid 3D FFT of ncols grids: sign -1 forward, +1 inverse, unnormalised
+void launch_grid_fft(int N, int plan, int sign, z64* data, long long stride, int ncols,
+                     const z64* tw, hipStream_t st);
+// coefficients *= scale (sqrt(4 pi) / |G|)^power inside 0 < |m|^2 <= m2max, 0 elsewhere
+void launch_coulomb_filter(z64* data, long long stride, int ncols, int N, int m2max, double b,
+                           int power, double scale, hipStream_t st);
+void launch_real_to_z(const double* in, long long istride, z64* out, long long ostride,
+                      long long n, int ncols, hipStream_t st);
+void launch_z_to_real(const z64* in, long long istride, double* out, long long ostride,
+                      long long n, int ncols, hipStream_t st);
+// C[i][j] = w <A_i, B_j> for i < na, j < nb
+void launch_gram(const double* A, long long lda, int na, const double* B, long long ldb, int nb,
+                 long long n, double w, double* C, hipStream_t st);
+// Y_j = beta Y_j + sum_{i < m} X_i C[i][j] for j < k (Y must not alias X)
+void launch_combine(const double* X, long long ldx, int m, const double* C, int k, long long n,
+                    double beta, double* Y, long long ldy, hipStream_t st);
+// R_j = AY_j - lam_j Y_j for j < k (lam on the device)
+void launch_ritz_resid(const double* AY, const double* Y, long long ld, const double* lam, int k,
+                       long long n, double* R, hipStream_t st);
+void launch_scale_vec(double* x, long long n, double s, hipStream_t st);
+
 }  // namespace sth
