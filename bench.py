@@ -175,6 +175,48 @@ def served(args):
     print(json.dumps(out))
 
 
+# ---------------------------------------------------------------- dielectric eigensolver
+def pdep_run(args):
+    """Lowest eigenpairs of chi_bar0 = v^{1/2} chi0 v^{1/2} by the device Davidson
+    (sth_pdep) on one system; prints one JSON line with the wall time, the Davidson
+    iterations, the solves it ran and the kernel phases of those solves."""
+    import torch  # noqa: F401  (device runtime of the process)
+    import paper_2203_05623_amd as P
+
+    cfg = workloads.get_config(args.config)
+    miller = workloads.miller_sphere(cfg.M2)
+    vloc = workloads.vloc_r(cfg)
+    beta = workloads.beta_projectors(cfg, miller)
+    dij = workloads.dij(cfg)
+    ctx = P.sth_create(device=0, max_slots=args.slots)
+    if args.valence_cache and os.path.exists(args.valence_cache):
+        d = np.load(args.valence_cache)
+        eps, psi = d["eps"], d["psi"]
+    else:
+        eps, psi, _, _ = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, cfg.nv + 1,
+                                       tol=1e-10)
+        if args.valence_cache:
+            np.savez(args.valence_cache, eps=eps, psi=psi, res=0.0, iters=0)
+    sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
+                           eps[:cfg.nv])
+    prec = PRECISIONS[args.precision](P)
+    P.sth_profile(ctx, True)
+    t0 = time.perf_counter()
+    lam, _, its, res = P.sth_pdep(ctx, sid, cfg.N, args.npdep, tol=args.pdep_tol, maxit=200,
+                                  solve_tol=args.tol, precision=prec, want_vectors=False)
+    dt = time.perf_counter() - t0
+    prof = P.sth_profile_read(ctx)
+    P.sth_destroy(ctx)
+    kernel_ms = sum(v[0] for v in prof.values())
+    out = {"mode": "pdep", "config": args.config, "grid": cfg.N, "bands": cfg.nv,
+           "npdep": args.npdep, "precision": args.precision, "solve_tol": args.tol,
+           "davidson_tol": args.pdep_tol, "iterations": its, "max_residual": res,
+           "seconds": dt, "eigenvalues_lowest": [float(x) for x in lam[:8]],
+           "solve_kernel_ms": round(kernel_ms, 1),
+           "phases_ms": {k: round(v[0], 1) for k, v in prof.items()}}
+    print(json.dumps(out))
+
+
 # ---------------------------------------------------------------- GPU run
 def main():
     ap = argparse.ArgumentParser()
@@ -197,6 +239,10 @@ def main():
                     help="served mode: Poisson request stream over several systems")
     ap.add_argument("--served-systems", default="cfg4a,cfg4b,cfg4c")
     ap.add_argument("--served-requests", type=int, default=40)
+    ap.add_argument("--pdep", action="store_true",
+                    help="dielectric eigensolver: lowest eigenpairs of v^1/2 chi0 v^1/2")
+    ap.add_argument("--npdep", type=int, default=32)
+    ap.add_argument("--pdep-tol", type=float, default=1e-5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for "
@@ -205,6 +251,9 @@ def main():
         sys.exit(2)
     if args.served:
         served(args)
+        return
+    if args.pdep:
+        pdep_run(args)
         return
     cfg = workloads.get_config(args.config)
     npert = args.npert or cfg.npert

@@ -240,7 +240,8 @@ sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket);
  * direction remains.  eig_out [npdep] ascending, host memory; vec_out (may be
  * NULL) real [npdep][n^3] orthonormal eigenvectors (C order) in `vec_ptr_kind`
  * memory; *iters and *max_resid (may be NULL) report the run (max_resid > tol:
- * not converged).  Grids up to 96.  STH_E_INVALID for bad arguments. */
+ * not converged).  Grids up to 96.  STH_E_INVALID for bad arguments.  With
+ * STH_VERBOSE=1 each iteration prints one progress line to stderr. */
 sth_status sth_pdep(sth_ctx* ctx, int32_t system_id, int npdep, int nmax, double tol, int maxit,
                     double solve_tol, int precision, double* eig_out, double* vec_out,
                     int vec_ptr_kind, void* stream, int* iters, double* max_resid);

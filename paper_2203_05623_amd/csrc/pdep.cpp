@@ -16,6 +16,8 @@
 // Converged when every one of the npdep lowest Ritz pairs has ||r_k|| <= tol.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <vector>
@@ -50,6 +52,9 @@ void Context::pdep(int id, int npdep, int nmax, double tol, int maxit, double so
               "solve_tol > 0, eig_out, and a valid precision");
     throw Error(STH_E_INVALID);
   }
+  // STH_VERBOSE=1: one progress line per iteration on stderr
+  const char* ve = std::getenv("STH_VERBOSE");
+  const bool verbose = ve && std::atoi(ve) != 0;
   int N = 0, nv = 0, m2d = 0, plan = 0;
   double omega = 0.0, b = 0.0;
   const z64* tw = nullptr;
@@ -233,6 +238,9 @@ void Context::pdep(int id, int npdep, int nmax, double tol, int maxit, double so
       set_error("pdep: non-finite residual");
       throw Error(STH_E_INTERNAL);
     }
+    if (verbose)
+      std::fprintf(stderr, "pdep: iteration %d, basis %d, max residual %.3e, lowest %.10f\n", it,
+                   m, res, lam[0]);
     if (res <= tol) break;
     if (it == maxit) break;
     // restart from the Ritz vectors when the new directions would not fit
