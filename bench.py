@@ -217,6 +217,45 @@ def pdep_run(args):
     print(json.dumps(out))
 
 
+# ---------------------------------------------------------------- Lanczos chains
+def lanczos_run(args):
+    """Batched Lanczos chains (sth_lanczos) of one orbital for --nphi band-limited real
+    grid functions, --nsteps steps; prints one JSON line with the wall time per call
+    (after one warm-up call) and the H applications per second."""
+    import torch  # noqa: F401  (device runtime of the process)
+    import paper_2203_05623_amd as P
+
+    cfg = workloads.get_config(args.config)
+    miller = workloads.miller_sphere(cfg.M2)
+    vloc = workloads.vloc_r(cfg)
+    beta = workloads.beta_projectors(cfg, miller)
+    dij = workloads.dij(cfg)
+    ctx = P.sth_create(device=0, max_slots=args.slots)
+    if args.valence_cache and os.path.exists(args.valence_cache):
+        d = np.load(args.valence_cache)
+        eps, psi = d["eps"], d["psi"]
+    else:
+        eps, psi, _, _ = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, cfg.nv + 1,
+                                       tol=1e-10)
+        if args.valence_cache:
+            np.savez(args.valence_cache, eps=eps, psi=psi, res=0.0, iters=0)
+    sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
+                           eps[:cfg.nv])
+    # smooth real functions on the grid (perturbation-shaped stand-ins for PDEP vectors)
+    phi = workloads.dv_block(cfg, range(args.nphi))
+    band = cfg.nv - 1
+    P.sth_lanczos(ctx, sid, band, phi, args.nsteps)
+    t0 = time.perf_counter()
+    a, b, dd, U, br = P.sth_lanczos(ctx, sid, band, phi, args.nsteps)
+    dt = time.perf_counter() - t0
+    P.sth_destroy(ctx)
+    out = {"mode": "lanczos", "config": args.config, "grid": cfg.N, "band": band,
+           "chains": args.nphi, "steps": args.nsteps, "seconds": dt,
+           "h_applications_per_s": args.nphi * args.nsteps / dt,
+           "alpha_first": [float(x) for x in a[0, :4]], "beta_first": [float(x) for x in b[0, :4]]}
+    print(json.dumps(out))
+
+
 # ---------------------------------------------------------------- GPU run
 def main():
     ap = argparse.ArgumentParser()
@@ -243,6 +282,10 @@ def main():
                     help="dielectric eigensolver: lowest eigenpairs of v^1/2 chi0 v^1/2")
     ap.add_argument("--npdep", type=int, default=32)
     ap.add_argument("--pdep-tol", type=float, default=1e-5)
+    ap.add_argument("--lanczos", action="store_true",
+                    help="batched Lanczos chains of one orbital (--nphi chains, --nsteps steps)")
+    ap.add_argument("--nphi", type=int, default=64)
+    ap.add_argument("--nsteps", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for "
@@ -254,6 +297,9 @@ def main():
         return
     if args.pdep:
         pdep_run(args)
+        return
+    if args.lanczos:
+        lanczos_run(args)
         return
     cfg = workloads.get_config(args.config)
     npert = args.npert or cfg.npert

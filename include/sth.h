@@ -246,6 +246,24 @@ sth_status sth_pdep(sth_ctx* ctx, int32_t system_id, int npdep, int nmax, double
                     double solve_tol, int precision, double* eig_out, double* vec_out,
                     int vec_ptr_kind, void* stream, int* iters, double* max_resid);
 
+/* Lanczos chains of orbital `band` for nphi real grid functions phi (paper,
+ * Section 3, equation "lanczos" and the recurrences before it; Section 4.3 for
+ * the braket product).  Chain m starts from u_m = T_S[phi_m psi_band] (product
+ * in real space, coefficients on the sphere) and runs nsteps steps of
+ *   alpha^l = <q^l|H|q^l>,  r = (H - alpha^l) q^l - beta^l q^{l-1},
+ *   r -= sum_{k<=l} <q^k|r> q^k,  beta^{l+1} = ||r||,  q^{l+1} = r / beta^{l+1},
+ * q^1 = u_m / ||u_m||, H the FP64 dual-space Hamiltonian of the system.
+ * phi: real [nphi][n^3] in `ptr_kind` memory.  Outputs in host memory, row-major:
+ * alpha [nphi][nsteps]; beta [nphi][nsteps] with beta[m][0] = ||u_m|| and
+ * beta[m][l] (l >= 1) the off-diagonal of the tridiagonal matrix between steps
+ * l-1 and l; d [nphi][nsteps] its ascending eigenvalues and U
+ * [nphi][nsteps][nsteps] its eigenvectors as columns (d, U may be NULL);
+ * braket complex128 [nphi][nphi][nsteps]: <u_n|q^l_m> at [n][m][l] (may be NULL).
+ * 1 <= nphi <= 256, 1 <= nsteps <= 200; STH_E_INTERNAL if a chain breaks down. */
+sth_status sth_lanczos(sth_ctx* ctx, int32_t system_id, int band, int nphi, const double* phi,
+                       int ptr_kind, int nsteps, double* alpha, double* beta, double* d,
+                       double* U, double* braket, void* stream);
+
 /* Kernel timing of the solve server, for measurement: with enable != 0 the
  * library records HIP events (on its own stream) around every kernel launch
  * of the CG iterations, grouped by phase:

@@ -6,12 +6,13 @@ The computation lives in the HIP library ``libsth.so`` (C-ABI in include/sth.h);
 from . import _lib
 from ._lib import (STH_FP64, STH_MIXED, STH_MIXED_BF16, SthError, sth_apply_h, sth_chi0_block,
                    sth_create, sth_destroy, sth_fetch_drho, sth_fetch_dpsi, sth_fetch_stats,
-                   sth_last_error, sth_pdep, sth_poll, sth_profile, sth_profile_read, sth_release_system,
-                   sth_release_ticket, sth_set_system, sth_submit_solves, sth_system_info_get,
-                   sth_valence, sth_wait)
+                   sth_lanczos, sth_last_error, sth_pdep, sth_poll, sth_profile,
+                   sth_profile_read, sth_release_system, sth_release_ticket, sth_set_system,
+                   sth_submit_solves, sth_system_info_get, sth_valence, sth_wait)
 
 __all__ = ["STH_FP64", "STH_MIXED", "STH_MIXED_BF16", "SthError", "sth_apply_h",
            "sth_chi0_block", "sth_create", "sth_destroy", "sth_fetch_drho", "sth_fetch_dpsi",
-           "sth_fetch_stats", "sth_last_error", "sth_pdep", "sth_poll", "sth_profile", "sth_profile_read",
-           "sth_release_system", "sth_release_ticket", "sth_set_system", "sth_submit_solves",
-           "sth_system_info_get", "sth_valence", "sth_wait", "_lib"]
+           "sth_fetch_stats", "sth_lanczos", "sth_last_error", "sth_pdep", "sth_poll",
+           "sth_profile", "sth_profile_read", "sth_release_system", "sth_release_ticket",
+           "sth_set_system", "sth_submit_solves", "sth_system_info_get", "sth_valence",
+           "sth_wait", "_lib"]

@@ -25,7 +25,8 @@ SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
            "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
            "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
-           "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_pdep", "sth_last_error"]
+           "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_pdep", "sth_lanczos",
+           "sth_last_error"]
 PHASES = ["zfft_inv", "plane", "zfft_fwd", "gemm_ah_b", "reduce", "gemm_a_c", "cg", "rhs_retire"]
 
 
@@ -96,6 +97,7 @@ def load():
         "sth_system_info_get": [vp, i32, C.POINTER(sth_system_info)],
         "sth_pdep": [vp, i32, C.c_int, C.c_int, dbl, C.c_int, dbl, C.c_int, vp, vp, C.c_int, vp,
                      C.POINTER(C.c_int), C.POINTER(dbl)],
+        "sth_lanczos": [vp, i32, C.c_int, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -298,6 +300,23 @@ def sth_chi0_block(ctx, ticket, npert):
 
 def sth_release_ticket(ctx, ticket):
     _check(lib().sth_release_ticket(ctx, ticket))
+
+
+def sth_lanczos(ctx, system_id, band, phi, nsteps):
+    """Lanczos chains of orbital `band` for the real grids phi [nphi, n, n, n]:
+    (alpha, beta, d [nphi, nsteps], U [nphi, nsteps, nsteps], braket [nphi, nphi, nsteps])."""
+    nphi = int(phi.shape[0])
+    p, kind, keep = _ptr(phi, np.float64)
+    alpha = np.empty((nphi, nsteps))
+    beta = np.empty((nphi, nsteps))
+    d = np.empty((nphi, nsteps))
+    U = np.empty((nphi, nsteps, nsteps))
+    br = np.empty((nphi, nphi, nsteps), np.complex128)
+    _check(lib().sth_lanczos(ctx, system_id, band, nphi, p, kind, nsteps, alpha.ctypes.data,
+                             beta.ctypes.data, d.ctypes.data, U.ctypes.data, br.ctypes.data,
+                             _stream(phi)))
+    del keep
+    return alpha, beta, d, U, br
 
 
 def sth_pdep(ctx, system_id, n, npdep, nmax=0, tol=1e-6, maxit=100, solve_tol=1e-10,

@@ -183,6 +183,15 @@ sth_status sth_pdep(sth_ctx* ctx, int32_t system_id, int npdep, int nmax, double
   });
 }
 
+sth_status sth_lanczos(sth_ctx* ctx, int32_t system_id, int band, int nphi, const double* phi,
+                       int ptr_kind, int nsteps, double* alpha, double* beta, double* d,
+                       double* U, double* braket, void* stream) {
+  return guard([&] {
+    ctx_of(ctx)->lanczos(system_id, band, nphi, phi, ptr_kind, nsteps, alpha, beta, d, U, braket,
+                         static_cast<hipStream_t>(stream));
+  });
+}
+
 sth_status sth_release_ticket(sth_ctx* ctx, uint64_t ticket) {
   return guard([&] { ctx_of(ctx)->release_ticket(ticket); });
 }

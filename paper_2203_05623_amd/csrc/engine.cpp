@@ -90,15 +90,6 @@ HostMem::~HostMem() {
 
 namespace {
 
-template <typename T>
-DevMem upload(Budget* b, const std::vector<T>& v, hipStream_t st) {
-  DevMem m(b, v.size() * sizeof(T));
-  if (!v.empty())
-    STH_HIP_CHECK(hipMemcpyAsync(m.as<void>(), v.data(), v.size() * sizeof(T),
-                                 hipMemcpyHostToDevice, st));
-  return m;
-}
-
 int imod(int a, int n) { return ((a % n) + n) % n; }
 
 }  // namespace

@@ -101,6 +101,16 @@ void gen_eig_device(Budget* b, const std::vector<double>& M, const std::vector<d
 
 struct Request;
 
+// A host vector copied into a new device allocation (stream-ordered on st).
+template <typename T>
+DevMem upload(Budget* b, const std::vector<T>& v, hipStream_t st) {
+  DevMem m(b, v.size() * sizeof(T));
+  if (!v.empty())
+    STH_HIP_CHECK(hipMemcpyAsync(m.as<void>(), v.data(), v.size() * sizeof(T),
+                                 hipMemcpyHostToDevice, st));
+  return m;
+}
+
 // Copies between caller memory (STH_PTR_HOST or STH_PTR_DEVICE) and device memory,
 // stream-ordered on st; check_ptr_kind rejects any other kind (STH_E_INVALID).
 void copy_in(void* dst, const void* src, size_t bytes, int ptr_kind, hipStream_t st);
@@ -227,6 +237,9 @@ class Context {
   void pdep(int id, int npdep, int nmax, double tol, int maxit, double solve_tol, int precision,
             double* eig_out, double* vec_out, int ptr_kind, hipStream_t user, int* iters,
             double* max_resid);
+  void lanczos(int id, int band, int nphi, const double* phi, int ptr_kind, int nsteps,
+               double* alpha, double* beta, double* d, double* U, double* braket,
+               hipStream_t user);
 
  private:
   void autotune(System& s);

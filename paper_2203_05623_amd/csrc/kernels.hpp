@@ -218,4 +218,18 @@ void launch_ritz_resid(const double* AY, const double* Y, long long ld, const do
                        long long n, double* R, hipStream_t st);
 void launch_scale_vec(double* x, long long n, double s, hipStream_t st);
 
+// ---- Lanczos chains (complex vectors of length n; chain vector (k, m) at
+// X + k xs_k + m xs_m) ----
+// out[m * ldo + k] = <X_{k,m}|Y_m> for k < nk, m < nm
+void launch_chain_dots(const z64* X, long long xs_k, long long xs_m, int nk, const z64* Y,
+                       long long ys_m, int nm, int n, z64* out, int ldo, hipStream_t st);
+// r_m = Hq_m - Re(alpha_m) q_m - beta_m qprev_m (qprev may be null)
+void launch_lanczos_three_term(const z64* Hq, const z64* q, const z64* qprev, const z64* alpha,
+                               const double* beta, int nm, int n, z64* r, hipStream_t st);
+// r_m -= sum_{k < l} c[m * ldc + k] Q_{k,m}   (Q vectors contiguous: (k nm + m) n)
+void launch_chain_orth(const z64* Q, int nm, int n, const z64* c, int ldc, int l, z64* r,
+                       hipStream_t st);
+// out_m = in_m / s[m]
+void launch_chain_div(const z64* in, const double* s, int nm, int n, z64* out, hipStream_t st);
+
 }  // namespace sth
