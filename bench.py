@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--npert", type=int, default=0, help="override the perturbation count")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
+    ap.add_argument("--compare", default="mixed-bf16", choices=sorted(PRECISIONS) + [""],
+                    help="also time this precision on the same system (empty: skip)")
     ap.add_argument("--slots", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
@@ -377,6 +379,35 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = P.sth_profile_read(ctx)
+    P.sth_profile(ctx, False)
+    # the other precision of the metric on the same system and inputs (its own
+    # warm-up step captures its graphs), reported beside the primary figure
+    compare = None
+    if args.compare and args.compare != args.precision:
+        prec = PRECISIONS[args.compare](P)
+        for _ in range(max(args.warmup, 1)):
+            step()
+        print(f"{args.compare} warmup step done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c_lat, c_its, c_bad, c_worst = [], [], 0, 0.0
+        for k in range(args.steps):
+            info, it, res, st, lt, _ = step()
+            c_lat.append(lt)
+            c_its.append(it)
+            c_bad += int((st != 0).sum())
+            c_worst = max(c_worst, float(res.max()))
+            print(f"{args.compare} step {k} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - t1
+        cl = np.concatenate(c_lat) * 1e3
+        ci = np.concatenate(c_its)
+        compare = {"precision": args.compare, "value": args.steps * nsolves / cdt,
+                   "ms_per_step": cdt * 1e3 / args.steps,
+                   "latency_ms": {"p50": float(np.percentile(cl, 50)),
+                                  "p99": float(np.percentile(cl, 99))},
+                   "cg_iterations": {"mean": float(ci.mean()), "max": int(ci.max())},
+                   "not_converged": c_bad, "max_true_rel_residual": c_worst}
     P.sth_destroy(ctx)
 
     lat = np.concatenate(lats) * 1e3
@@ -428,6 +459,9 @@ def main():
                   "gap_Ha": gap},
         "roofline": roof, "phases": phases, "tuning": tuning, "cpu_baseline": cpu,
     }
+    if compare is not None:
+        compare["speedup_over_" + args.precision] = compare["value"] / value
+        out["compare"] = compare
     print(json.dumps(out))
 
 
