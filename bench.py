@@ -31,6 +31,7 @@ METRIC = "Sternheimer solves/s, FP64 vs mixed at 1e-8 residual; p50/p99 solve la
 MI355X_HBM_GBS = 8000.0
 MI355X_FP64_TFLOPS = 78.6     # FP64 vector ALU and FP64 dense MFMA
 MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
+MI355X_BF16_TFLOPS = 2500.0   # BF16 dense MFMA
 # (phase, precision) -> measured HBM bytes / algorithmic bytes of its kernel
 # (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
 # whenever the kernel changes
@@ -416,7 +417,9 @@ def main():
     # dominant kernel phase and its roofline: the projector GEMMs against the
     # MFMA peak, the plane stage (FFT butterflies on the vector ALUs) against the
     # vector ALU peak with the nominal 5 N log2 N flops per transform, the other
-    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed
+    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed.  The
+    # BF16 split GEMMs take the BF16 MFMA peak: their algorithmic (complex FP32)
+    # flops are issued as three BF16 products (hi hi, hi lo, lo hi)
     dom = max(prof, key=lambda k: prof[k][0])
     ms, nl, by, fl = prof[dom]
     kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
@@ -424,9 +427,16 @@ def main():
         roof = {"bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9, "peak": MI355X_HBM_GBS,
                 "unit": "GB/s"}
     else:
-        peak = MI355X_FP64_TFLOPS if args.precision == "fp64" else MI355X_FP32_TFLOPS
+        if args.precision == "fp64":
+            peak = MI355X_FP64_TFLOPS
+        elif kind == "mfma" and args.precision == "mixed-bf16":
+            peak = MI355X_BF16_TFLOPS
+        else:
+            peak = MI355X_FP32_TFLOPS
         roof = {"bound": kind, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak,
                 "unit": "TFLOP/s"}
+        if kind == "mfma" and args.precision == "mixed-bf16":
+            roof["mfma_products_per_flop"] = 3
     roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (calibrated
     # on a 1 GiB copy) as a multiple of the algorithmic bytes, where measured

@@ -175,12 +175,18 @@ sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* 
                        double* out, int ptr_kind, void* stream);
 
 /* Lowest nbands eigenpairs of H for a system description whose psi_v / eps_v
- * are ignored (nv may be 0), by block LOBPCG on the device with FP64
- * Rayleigh-Ritz.  eps_out [nbands], psi_out complex128 [nbands][npw] (caller
- * order), both in `out_ptr_kind` memory.  Converged when every residual
- * ||H x - theta x|| <= tol.  *iters and *max_resid report the run.  With the
- * environment variable STH_VERBOSE=1 each iteration prints one progress line
- * (iteration, largest residual, elapsed seconds) to stderr. */
+ * are ignored (nv may be 0), on the device with FP64 Rayleigh-Ritz: block
+ * LOBPCG on nbands + 8 vectors while 3 (nbands + 8) <= 2048, else
+ * Chebyshev-filtered subspace iteration (degree 16, Zhou-Saad scaled
+ * recurrence, spectrum upper bound from a 12-step Lanczos run) on
+ * nbands + max(8, nbands / 10) vectors; the environment variable
+ * STH_VALENCE=lobpcg or chfsi forces one.  Needs 3 (nbands + 8) <= npw
+ * (LOBPCG) or 2 nb <= npw (subspace iteration), else STH_E_INVALID.
+ * eps_out [nbands], psi_out complex128 [nbands][npw] (caller order), both in
+ * `out_ptr_kind` memory.  Converged when every residual ||H x - theta x|| <= tol.
+ * *iters and *max_resid report the run.  With the environment variable
+ * STH_VERBOSE=1 each iteration prints one progress line (iteration, largest
+ * residual, elapsed seconds) to stderr. */
 sth_status sth_valence(sth_ctx* ctx, const sth_system_desc* desc, int nbands, double tol,
                        int maxit, double* eps_out, double* psi_out, int out_ptr_kind,
                        double* max_resid, int* iters);

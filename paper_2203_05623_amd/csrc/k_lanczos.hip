@@ -86,9 +86,32 @@ __global__ void k_chain_div(const z64* in, const double* s, int nm, int n, z64* 
   out[t] = z64{in[t].x * f, in[t].y * f};
 }
 
+// out = a A + b B + c C over n complex elements (C may be null); out may alias C
+__global__ void k_block_axpbypcz(long long n, double a, const z64* A, double b, const z64* B,
+                                 double c, const z64* C, z64* out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const z64 x = A[t], y = B[t];
+  double re = a * x.x + b * y.x, im = a * x.y + b * y.y;
+  if (C) {
+    const z64 z = C[t];
+    re += c * z.x;
+    im += c * z.y;
+  }
+  out[t] = z64{re, im};
+}
+
 inline unsigned nblk(long long n, int b) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
+
+void launch_block_axpbypcz(long long n, double a, const z64* A, double b, const z64* B, double c,
+                           const z64* C, z64* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_block_axpbypcz, dim3(nblk(n, 256)), dim3(256), 0, st, n, a, A, b, B, c, C,
+                     out);
+  STH_HIP_CHECK(hipGetLastError());
+}
 
 void launch_chain_dots(const z64* X, long long xs_k, long long xs_m, int nk, const z64* Y,
                        long long ys_m, int nm, int n, z64* out, int ldo, hipStream_t st) {

@@ -231,5 +231,8 @@ void launch_chain_orth(const z64* Q, int nm, int n, const z64* c, int ldc, int l
                        hipStream_t st);
 // out_m = in_m / s[m]
 void launch_chain_div(const z64* in, const double* s, int nm, int n, z64* out, hipStream_t st);
+// out = a A + b B + c C over n complex elements (C may be null; out may alias C)
+void launch_block_axpbypcz(long long n, double a, const z64* A, double b, const z64* B, double c,
+                           const z64* C, z64* out, hipStream_t st);
 
 }  // namespace sth

@@ -12,6 +12,14 @@
 // Subspace products are complex GEMMs on the FP64 matrix cores, the small
 // eigenproblems run on the device Jacobi solver.  A block of nbands + 8
 // vectors is iterated; the lowest nbands must meet the tolerance.
+//
+// For many bands (3 (nbands + 8) beyond the Jacobi solver's comfortable size)
+// the same routine runs Chebyshev-filtered subspace iteration instead (Zhou and
+// Saad's filtered Rayleigh-Ritz): Rayleigh-Ritz problems of only nb vectors,
+// each iteration a degree-16 filter in the scaled three-term recurrence (15
+// block H applications), orthonormalisation, one H application and
+// Rayleigh-Ritz.  The filter damps [theta_nb, b] with b an upper bound of the
+// spectrum; the block carries about 10% guard vectors.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,6 +35,9 @@
 namespace sth {
 
 namespace {
+
+constexpr int kLobpcgMaxDim = 2048;   // largest LOBPCG Rayleigh-Ritz problem (3 nb)
+constexpr int kChebDegree = 16;       // Chebyshev filter degree of the subspace iteration
 
 struct Lobpcg {
   Context& ctx;
@@ -153,10 +164,21 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
     set_error("unsupported grid n=%d (supported: 24, 48, 72, 96, 144)", d.n);
     throw Error(STH_E_INVALID);
   }
-  const int guard = 8;
+  // block LOBPCG while its Rayleigh-Ritz problems (3 (nbands + 8)) stay small for
+  // the Jacobi eigensolver, Chebyshev-filtered subspace iteration (problems of nb)
+  // beyond; STH_VALENCE=lobpcg or chfsi forces one
+  const char* va = std::getenv("STH_VALENCE");
+  const bool chfsi = va && std::strcmp(va, "chfsi") == 0   ? true
+                     : va && std::strcmp(va, "lobpcg") == 0 ? false
+                                                            : 3 * (nbands + 8) > kLobpcgMaxDim;
+  // guard vectors above the wanted bands: the filter's convergence factor for
+  // band nbands is set by the spectral distance to the top of the block, so the
+  // subspace iteration keeps about 10% more
+  const int guard = chfsi ? std::max(8, nbands / 10) : 8;
   const int nb = nbands + guard;
-  if (nbands <= 0 || 3 * nb > d.npw) {
-    set_error("valence: need 0 < 3 (nbands + 8) <= npw");
+  if (nbands <= 0 || (chfsi ? 2 * nb : 3 * nb) > d.npw) {
+    set_error("valence: need 0 < 3 (nbands + 8) <= npw (LOBPCG) or 2 (nbands + guard) <= npw "
+              "(subspace iteration, guard = max(8, nbands / 10))");
     throw Error(STH_E_INVALID);
   }
   if (maxit <= 0) maxit = 500;
@@ -171,10 +193,15 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
   const int n = s.npw;
   HScratch hw;
   h_scratch(s, hw, std::min(nb, 256));
-  Lobpcg L(*this, s, hw, 3 * nb);
+  Lobpcg L(*this, s, hw, chfsi ? nb : 3 * nb);
   const size_t vb = (size_t)n * sizeof(z64);
-  DevMem S(&budget_, 3 * (size_t)nb * vb), HS(&budget_, 3 * (size_t)nb * vb);
-  DevMem P(&budget_, (size_t)nb * vb), HP(&budget_, (size_t)nb * vb);
+  const int nblock = chfsi ? 1 : 3;   // blocks of nb vectors in S and HS
+  DevMem S(&budget_, nblock * (size_t)nb * vb), HS(&budget_, nblock * (size_t)nb * vb);
+  DevMem P, HP;
+  if (!chfsi) {
+    P = DevMem(&budget_, (size_t)nb * vb);
+    HP = DevMem(&budget_, (size_t)nb * vb);
+  }
   z64* X = S.as<z64>();
   z64* HX = HS.as<z64>();
 
@@ -200,7 +227,134 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
   std::vector<double> th, rn(nb);
   double res = INFINITY;
   int it = 0;
-  for (; it < maxit; ++it) {
+  auto progress = [&]() {
+    if (verbose)
+      std::fprintf(stderr, "valence: iteration %d, max residual %.3e, %.1f s\n", it, res,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
+                       .count());
+    if (!(res == res)) {
+      set_error("valence: non-finite residual");
+      throw Error(STH_E_INTERNAL);
+    }
+  };
+  DevMem Yb, Zb, HY;   // Chebyshev filter blocks (ChFSI only)
+  if (chfsi) {
+    // Chebyshev-filtered subspace iteration (Zhou & Saad): each iteration applies
+    // the degree-kChebDegree Chebyshev polynomial of H that is small on
+    // [theta_nb, upper bound of the spectrum] and large below it, in its scaled
+    // three-term form, then orthonormalises and does Rayleigh-Ritz on the nb
+    // filtered vectors.
+    Yb = DevMem(&budget_, (size_t)nb * vb);
+    Zb = DevMem(&budget_, (size_t)nb * vb);
+    HY = DevMem(&budget_, (size_t)nb * vb);
+    const long long nel = (long long)nb * n;
+    // upper bound of the spectrum: a few Lanczos steps on one vector; Gershgorin
+    // of their tridiagonal matrix plus the last residual norm
+    double bup = 0.0;
+    {
+      constexpr int K = 12;
+      std::mt19937_64 rng(11);
+      std::normal_distribution<double> nd(0.0, 1.0);
+      std::vector<z64> v(n), w(n), vp(n, z64{0.0, 0.0});
+      double nrm = 0.0;
+      for (auto& x : v) {
+        x = z64{nd(rng), nd(rng)};
+        nrm += x.x * x.x + x.y * x.y;
+      }
+      for (auto& x : v) x = z64{x.x / std::sqrt(nrm), x.y / std::sqrt(nrm)};
+      std::vector<double> al(K), be(K + 1, 0.0);
+      int kk = K;
+      z64* dv = Yb.as<z64>();
+      z64* dw = Zb.as<z64>();
+      for (int k = 0; k < K; ++k) {
+        STH_HIP_CHECK(hipMemcpyAsync(dv, v.data(), vb, hipMemcpyHostToDevice, st_));
+        h_block(s, hw, dv, dw, 1);
+        STH_HIP_CHECK(hipMemcpyAsync(w.data(), dw, vb, hipMemcpyDeviceToHost, st_));
+        STH_HIP_CHECK(hipStreamSynchronize(st_));
+        double a = 0.0;
+        for (int g = 0; g < n; ++g) a += v[g].x * w[g].x + v[g].y * w[g].y;
+        double b2 = 0.0;
+        for (int g = 0; g < n; ++g) {
+          w[g].x -= a * v[g].x + be[k] * vp[g].x;
+          w[g].y -= a * v[g].y + be[k] * vp[g].y;
+          b2 += w[g].x * w[g].x + w[g].y * w[g].y;
+        }
+        al[k] = a;
+        be[k + 1] = std::sqrt(b2);
+        if (!(be[k + 1] > 1e-12 * std::fabs(a))) {   // invariant subspace: T is exact
+          kk = k + 1;
+          break;
+        }
+        vp = v;
+        for (int g = 0; g < n; ++g) v[g] = z64{w[g].x / be[k + 1], w[g].y / be[k + 1]};
+      }
+      // Gershgorin bound of the kk x kk tridiagonal matrix, plus the norm of the
+      // last residual
+      double gersh = -INFINITY;
+      for (int k = 0; k < kk; ++k)
+        gersh = std::max(gersh, al[k] + be[k] + (k + 1 < kk ? be[k + 1] : 0.0));
+      bup = gersh + be[kk];
+    }
+    z64* bufs[3] = {S.as<z64>(), Yb.as<z64>(), Zb.as<z64>()};
+    auto rr_rotate = [&]() {
+      L.rr(X, HX, nb, th);
+      launch_cols_to_rows(L.evec.as<z64>(), nb, 0, nb, 0, nb, nullptr, L.cmat.as<z64>(), st_);
+      L.combine(X, nb, L.cmat.as<z64>(), L.tmp1.as<z64>(), nb, 0.0);
+      L.combine(HX, nb, L.cmat.as<z64>(), L.tmp2.as<z64>(), nb, 0.0);
+      L.copy(X, L.tmp1.as<z64>(), nb);
+      L.copy(HX, L.tmp2.as<z64>(), nb);
+    };
+    rr_rotate();
+    double a0 = th[0];
+    for (; it < maxit; ++it) {
+      STH_HIP_CHECK(hipMemcpyAsync(L.theta.as<void>(), th.data(), nb * sizeof(double),
+                                   hipMemcpyHostToDevice, st_));
+      z64* spare[2];
+      for (int b = 0, k = 0; b < 3; ++b)
+        if (bufs[b] != X) spare[k++] = bufs[b];
+      launch_resid_precond(s.g, X, HX, L.theta.as<double>(), nb, spare[0],
+                           L.norms.as<double>(), st_);
+      STH_HIP_CHECK(hipMemcpyAsync(rn.data(), L.norms.as<void>(), nb * sizeof(double),
+                                   hipMemcpyDeviceToHost, st_));
+      STH_HIP_CHECK(hipStreamSynchronize(st_));
+      res = 0.0;
+      for (int i = 0; i < nbands; ++i) res = std::max(res, std::sqrt(rn[i]));
+      progress();
+      if (res <= tol) break;
+      const double a = th[nb - 1];
+      const double e = 0.5 * (bup - a), c = 0.5 * (bup + a);
+      if (!(e > 0.0)) {
+        set_error("valence: empty filter interval (upper bound %.6f, theta_nb %.6f)", bup, a);
+        throw Error(STH_E_INTERNAL);
+      }
+      double sigma = e / (a0 - c);
+      const double tau = 2.0 / sigma;
+      z64* xp = X;          // previous filtered block
+      z64* yc = spare[0];   // current
+      z64* yn = spare[1];   // next
+      launch_block_axpbypcz(nel, sigma / e, HX, -c * sigma / e, X, 0.0, nullptr, yc, st_);
+      for (int k = 2; k <= kChebDegree; ++k) {
+        h_block(s, hw, yc, HY.as<z64>(), nb);
+        const double sn = 1.0 / (tau - sigma);
+        launch_block_axpbypcz(nel, 2.0 * sn / e, HY.as<z64>(), -2.0 * c * sn / e, yc,
+                              -sigma * sn, xp, yn, st_);
+        z64* t = xp;
+        xp = yc;
+        yc = yn;
+        yn = t;
+        sigma = sn;
+      }
+      if (L.orth(yc, nb, nullptr, nullptr, 0, nullptr) != nb) {
+        set_error("valence: filtered block lost rank");
+        throw Error(STH_E_INTERNAL);
+      }
+      X = yc;
+      h_block(s, hw, X, HX, nb);
+      rr_rotate();
+      a0 = std::min(a0, th[0]);
+    }
+  }
+  for (; !chfsi && it < maxit; ++it) {
     if (it > 0 && it % 8 == 0) h_block(s, hw, X, HX, nb);   // refresh the carried products
     if (L.orth(X, nb, HX, nullptr, 0, nullptr) != nb) {
       set_error("valence: block lost rank");
@@ -223,14 +377,7 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
     STH_HIP_CHECK(hipStreamSynchronize(st_));
     res = 0.0;
     for (int i = 0; i < nbands; ++i) res = std::max(res, std::sqrt(rn[i]));
-    if (verbose)
-      std::fprintf(stderr, "valence: iteration %d, max residual %.3e, %.1f s\n", it, res,
-                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
-                       .count());
-    if (!(res == res)) {
-      set_error("valence: non-finite residual");
-      throw Error(STH_E_INTERNAL);
-    }
+    progress();
     if (res <= tol) break;
     const int nw = L.orth(Wd, nb, nullptr, X, nb, nullptr);
     h_block(s, hw, Wd, HX + (size_t)nb * n, nw);

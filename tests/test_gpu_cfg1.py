@@ -88,14 +88,17 @@ def test_solves_match_oracle(sth, cfg1, sys1):
     P.sth_release_ticket(ctx, t)
 
 
-def test_valence_lobpcg_matches_dense(sth, cfg1, cfg1_dense):
-    """Device LOBPCG eigenpairs of H vs dense diagonalisation (oracle)."""
+@pytest.mark.parametrize("alg", ["lobpcg", "chfsi"])
+def test_valence_lobpcg_matches_dense(sth, cfg1, cfg1_dense, alg, monkeypatch):
+    """Device eigenpairs of H (block LOBPCG, or Chebyshev-filtered subspace
+    iteration, forced through STH_VALENCE) vs dense diagonalisation (oracle)."""
     P, ctx = sth
     cfg, s, H, eps, Psi = cfg1
     H_, w, V = cfg1_dense
+    monkeypatch.setenv("STH_VALENCE", alg)
     e, psi, res, its = P.sth_valence(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij,
                                      NV + 1, tol=1e-11)
-    print("valence iters", its, "residual", res)
+    print(alg, "valence iters", its, "residual", res)
     assert res <= 1e-11
     assert np.abs(e - w[:NV + 1]).max() < 1e-11
     R = psi @ H.T - e[:, None] * psi

@@ -47,13 +47,16 @@ def sys2(sth, ref):
                             eps[:nv])
 
 
-def test_valence_matches_oracle(sth, ref):
-    """Device LOBPCG vs the oracle's LOBPCG: eigenvalues are gauge invariant."""
+@pytest.mark.parametrize("alg", ["lobpcg", "chfsi"])
+def test_valence_matches_oracle(sth, ref, alg, monkeypatch):
+    """Device eigensolver (block LOBPCG, or Chebyshev-filtered subspace
+    iteration) vs the oracle's LOBPCG: eigenvalues are gauge invariant."""
     P, ctx = sth
     s, eps, psi = ref
+    monkeypatch.setenv("STH_VALENCE", alg)
     e, v, res, its = P.sth_valence(ctx, CFG.L, CFG.N, s.miller, s.vloc_r, s.beta, s.dij,
                                    CFG.nv + 1, tol=1e-10)
-    print("device valence: iterations", its, "residual", res)
+    print(alg, "device valence: iterations", its, "residual", res)
     assert res <= 1e-10
     err = np.abs(e - eps[:CFG.nv + 1]).max()
     print("eigenvalue max abs diff", err, "gap", e[CFG.nv] - e[CFG.nv - 1])
