@@ -2,13 +2,12 @@
 // solve server that runs the batched preconditioned CG.
 //
 // Operator (paper, Section 3, the Sternheimer equation): for a solve of band v
-//   A x = (H - eps_v) x + alpha_pv P_v x,   b = -P_c (dV_j psi_v),
-// with P_v = sum_v |psi_v><psi_v| and alpha_pv > eps_max - eps_min.  On
-// range(P_c) A equals P_c (H - eps_v) P_c and b lies in range(P_c), so the
-// solution is the one of the projected equation; the shift makes A positive
-// definite on the whole sphere so that the Kleinman-Bylander projectors and
-// P_v enter through ONE pair of GEMMs with W = [psi_v; beta] and the diagonal
-// [alpha_pv, D_p].  The converged x is projected with P_c once more.
+//   P_c (H - eps_v) P_c x = b,   b = -P_c (dV_j psi_v),
+// with P_c = 1 - sum_v |psi_v><psi_v|.  The CG applies (H - eps_v) (FFT route
+// plus the Kleinman-Bylander GEMM pair) to directions kept in range(P_c) and
+// projects each result (an FP64 GEMM pair over the psi_v rows of
+// W = [psi_v; beta]); P_c (H - eps_v) P_c is positive definite there for a
+// band below the gap.  The converged x is projected with P_c once more.
 #include "engine.hpp"
 
 #include <algorithm>
@@ -378,7 +377,7 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.ntile = gemm_a_c_tiles(s.npw);
   s.nchunk = cg_chunks(s.npw);
 
-  // W = [psi_v; beta] in internal order, diag = [alpha_pv; D]
+  // W = [psi_v; beta] in internal order, diag = [0 on psi_v rows; D]
   s.d_W = DevMem(&budget_, (size_t)s.M * s.npw * sizeof(z64));
   {
     DevMem tmp(&budget_, (size_t)std::max({s.nv, s.nproj, 1}) * s.npw * sizeof(z64));
@@ -394,7 +393,7 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
     }
     STH_HIP_CHECK(hipStreamSynchronize(st_));
   }
-  std::vector<double> diag(s.M, s.alpha_pv);
+  std::vector<double> diag(s.M, 0.0);
   if (s.nproj) {
     std::vector<double> dij(s.nproj);
     if (d.ptr_kind == STH_PTR_DEVICE)
@@ -447,7 +446,6 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
       throw Error(STH_E_INVALID);
     }
   s.eps = eps;
-  s.alpha_pv = std::max(2.0 * (eps.back() - eps.front()), 1.0);
   StickBuild sb = setup_geometry(s, d, d.nv);
   const int N = s.N;
   const long long n3 = (long long)N * N * N;
@@ -568,17 +566,21 @@ static double plane_flops(const System& s, int n) {
   return double(n) * N * ((2.0 * s.nrow + 2.0 * N) * per_fft + 2.0 * N * N);
 }
 
-// out = (H - eps_slot) in + W diag W^H in, on the listed vectors (slot pool
-// scratch: sticks, part, C).  With `dots`, partial Re<in, out> per 64-row tile.
+// out = (H - eps_slot) in, on the listed vectors (slot pool scratch: sticks,
+// part, C): the FFT route for T + V_loc and the KB projector GEMMs
+// beta D beta^H in.  With `dots`, partial Re<in, out> per 64-row tile.  The CG
+// applies it to directions in range(P_c) and projects the result (project_c),
+// so that it runs on P_c (H - eps_v) P_c.
 void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
                        bool dots, int mode) {
   if (mode != OP_FP64) {
     apply_op32(s, in, out, dl, n, dots, mode == OP_BF16);
     return;
   }
-  const int N = s.N;
+  const int N = s.N, M = s.nproj;
   const double z = sizeof(z64), vb = double(s.npw) * z, sb = double(N) * s.nst * z;
-  const double gf = 8.0 * s.M * double(s.npw) * n;
+  const double gf = 8.0 * M * double(s.npw) * n;
+  const double* dkb = s.d_diag.as<double>() + s.nv;
   VecSet<z64> sticks{s.d_sticks.as<z64>(), (long long)N * s.nst};
   int h = prof_begin(PH_ZINV);
   launch_zfft_inv<double, z64>(s.g, in, sticks, dl, n, st_);
@@ -592,26 +594,30 @@ void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const i
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   // the GEMM partials are indexed by list position; the slot list maps them back
   h = prof_begin(PH_GEMM_AHB);
-  launch_gemm_ah_b(s.W(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, s.d_part.as<z64>(), st_);
-  prof_end(h, s.M * vb + n * vb, gf);
+  launch_gemm_ah_b(s.beta(), s.npw, M, in, dl, n, s.npw, s.kchunk, s.d_part.as<z64>(), st_);
+  prof_end(h, M * vb + n * vb, gf);
   h = prof_begin(PH_REDUCE);
-  launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.M, s.d_diag.as<double>(), 1.0,
-                      s.d_C.as<z64>(), st_);
-  prof_end(h, (s.nsplit + 1.0) * n * s.M * z, 0.0);
+  launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, M, dkb, 1.0, s.d_C.as<z64>(), st_);
+  prof_end(h, (s.nsplit + 1.0) * n * M * z, 0.0);
   h = prof_begin(PH_GEMM_AC);
-  launch_gemm_a_c(s.W(), s.npw, s.M, s.d_C.as<z64>(), out, dl, n, s.npw, 1.0, in,
+  launch_gemm_a_c(s.beta(), s.npw, M, s.d_C.as<z64>(), out, dl, n, s.npw, 1.0, in,
                   dots ? s.d_dots.as<double>() : nullptr, st_);
-  prof_end(h, s.M * vb + n * vb * (dots ? 3.0 : 2.0), gf);
+  prof_end(h, M * vb + n * vb * (dots ? 3.0 : 2.0), gf);
 }
 
 // The same operator with the FFT passes, V_loc and the projector GEMMs in FP32
-// (inner iterations of mixed-precision solves); the kinetic and shift terms
-// and every vector in memory stay FP64.
+// (inner iterations of mixed-precision solves); the kinetic and eps terms and
+// every vector in memory stay FP64.
 void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
                          bool dots, bool bf16) {
-  const int N = s.N;
+  const int N = s.N, M = s.nproj;
   const double vb = double(s.npw) * sizeof(z64), sb = double(N) * s.nst * sizeof(z32);
-  const double gf = 8.0 * s.M * double(s.npw) * n;
+  const double gf = 8.0 * M * double(s.npw) * n;
+  const double* dkb = s.d_diag.as<double>() + s.nv;
+  const int ldw = bf16_ldw(s.npw);
+  const bz* wb = s.d_Wb.as<bz>() + (size_t)s.nv * ldw;   // KB rows of the hi plane
+  const long long wplane = (long long)s.M * ldw;
+  const z32* w32 = s.d_W32.as<z32>() + (size_t)s.nv * s.npw;
   VecSet<z32> sticks{reinterpret_cast<z32*>(s.d_sticks.as<z64>()), (long long)N * s.nst};
   z32* part = reinterpret_cast<z32*>(s.d_part.as<z64>());
   z32* C = reinterpret_cast<z32*>(s.d_C.as<z64>());
@@ -627,22 +633,51 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   h = prof_begin(PH_GEMM_AHB);
   if (bf16)
-    launch_gemm_ah_b_bf16(s.d_Wb.as<bz>(), bf16_ldw(s.npw), s.M, in, dl, n, s.npw, s.kchunk, part,
-                          st_);
+    launch_gemm_ah_b_bf16(wb, wplane, ldw, M, in, dl, n, s.npw, s.kchunk, part, st_);
   else
-    launch_gemm_ah_b(s.d_W32.as<z32>(), s.npw, s.M, in, dl, n, s.npw, s.kchunk, part, st_);
-  prof_end(h, s.M * vb / 2 + n * vb, gf);
+    launch_gemm_ah_b(w32, s.npw, M, in, dl, n, s.npw, s.kchunk, part, st_);
+  prof_end(h, M * vb / 2 + n * vb, gf);
   h = prof_begin(PH_REDUCE);
-  launch_reduce_parts(part, s.nsplit, n, s.M, s.d_diag.as<double>(), 1.0, C, st_);
-  prof_end(h, (s.nsplit + 1.0) * n * s.M * sizeof(z32), 0.0);
+  launch_reduce_parts(part, s.nsplit, n, M, dkb, 1.0, C, st_);
+  prof_end(h, (s.nsplit + 1.0) * n * M * sizeof(z32), 0.0);
   h = prof_begin(PH_GEMM_AC);
   if (bf16)
-    launch_gemm_a_c_bf16(s.d_Wb.as<bz>(), bf16_ldw(s.npw), s.M, C, out, dl, n, s.npw, 1.0, in,
+    launch_gemm_a_c_bf16(wb, wplane, ldw, M, C, out, dl, n, s.npw, 1.0, in,
                          dots ? s.d_dots.as<double>() : nullptr, st_);
   else
-    launch_gemm_a_c(s.d_W32.as<z32>(), s.npw, s.M, C, out, dl, n, s.npw, 1.0, in,
+    launch_gemm_a_c(w32, s.npw, M, C, out, dl, n, s.npw, 1.0, in,
                     dots ? s.d_dots.as<double>() : nullptr, st_);
-  prof_end(h, s.M * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
+  prof_end(h, M * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
+}
+
+// Projection onto the conduction space, q <- q - Psi (Psi^H q), in FP64, on
+// the operator output q = (H - eps_v) p of every CG step and true residual.
+// The CG then runs on P_c (H - eps_v) P_c as the equation of Section 3 states
+// it: r stays in range(P_c), rho = <r, K r> = <r, P_c K r>, and the P_c part of
+// p = K r + beta p evolves exactly as the direction of a CG preconditioned by
+// P_c K P_c.  The P_v part of p is never used: P_c (H - eps_v) maps it to zero
+// (Psi are eigenvectors of H), the step length takes <p, P_c q> (partials in
+// `dots` with `dot_in` = p), and x's P_v part is removed when the solve
+// retires.  The projection is FP64 also in mixed solves: an FP32 / BF16 one
+// would leave a P_v remainder in r that the directions never remove, stalling
+// the inner runs.  (The alternative, a shifted operator H - eps_v + alpha P_v
+// on the whole sphere with K applied unprojected, needs no projection but about
+// 40% more iterations: K mixes P_v components into the CG's spectrum.)
+void Context::project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
+                        bool dots) {
+  const double vb = double(s.npw) * sizeof(z64);
+  const double gf = 8.0 * s.nv * double(s.npw) * n;
+  int h = prof_begin(PH_GEMM_AHB);
+  launch_gemm_ah_b(s.W(), s.npw, s.nv, {v.base, v.stride}, dl, n, s.npw, s.kchunk,
+                   s.d_part.as<z64>(), st_);
+  prof_end(h, s.nv * vb + n * vb, gf);
+  h = prof_begin(PH_REDUCE);
+  launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.nv, nullptr, -1.0, s.d_C.as<z64>(), st_);
+  prof_end(h, (s.nsplit + 1.0) * n * s.nv * sizeof(z64), 0.0);
+  h = prof_begin(PH_GEMM_AC);
+  launch_gemm_a_c(s.W(), s.npw, s.nv, s.d_C.as<z64>(), v, dl, n, s.npw, 1.0, dot_in,
+                  dots ? s.d_dots.as<double>() : nullptr, st_);
+  prof_end(h, s.nv * vb + n * vb * (dots ? 3.0 : 2.0), gf);
 }
 
 // ------------------------------------------------------------------ profiling
@@ -1115,7 +1150,8 @@ void Context::refill(System& s) {
 // convergence test, p = K r + beta p.
 void Context::cg_step(System& s, const int* dl, int n, int mode) {
   const double vb = double(s.npw) * sizeof(z64);
-  apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, true, mode);
+  apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, false, mode);
+  project_c(s, s.vec(s.d_q), dl, n, s.cvec(s.d_p), true);
   const int h = prof_begin(PH_CG);
   launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl, n, s.ss, st_);
   launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl, n, s.ss,
@@ -1187,10 +1223,15 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
   for (int i = 0; i < s.nslots; ++i)
     if (s.slots[i].req && h_status[i] == SLOT_CHECK) check.push_back(i);
   if (!check.empty()) {
-    // true residual r = b - A x for the candidates
     const int n = int(check.size());
+    // true residual r = P_c (b - (H - eps) P_c x) of the candidates.  x is
+    // projected first: the P_v parts of the directions it accumulated meet
+    // (H - eps) Psi = Psi (Lambda - eps) only as far as the valence states
+    // are eigenvectors, so they could bias the check
     int* dl = upload_list(s, check);
+    project_c(s, s.vec(s.d_x), dl, n, {nullptr, 0}, false);
     apply_op(s, s.cvec(s.d_x), s.vec(s.d_q), dl, n, false);
+    project_c(s, s.vec(s.d_q), dl, n, {nullptr, 0}, false);
     launch_cg_true_resid(s.g, s.cvec(s.d_b), s.cvec(s.d_q), s.vec(s.d_r), dl, n, s.ss.ekin,
                          s.d_part2.as<double>(), st_);
     launch_cg_check_true(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);

@@ -135,12 +135,12 @@ struct System {
   int id = 0;
   int N = 0, npw = 0, nst = 0, nrow = 0, nv = 0, nproj = 0, M = 0;
   int m2 = 0;          // largest |m|^2 on the sphere (density sphere: |m|^2 <= 4 m2)
-  double L = 0.0, omega = 0.0, fs = 2.0, alpha_pv = 0.0;
+  double L = 0.0, omega = 0.0, fs = 2.0;
   GridDev g;
   DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
   DevMem d_stage;      // [kStageSlots][nrow][N] z64 scratch planes of the strip-form kernels
   DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
-  DevMem d_diag;       // [nv + nproj]: alpha_pv on psi_v rows, D_p on beta rows
+  DevMem d_diag;       // [nv + nproj]: 0 on psi_v rows, D_p on beta rows
   DevMem d_vloc;       // [N^3] double
   DevMem d_W32;        // FP32 copy of W (inner operator of mixed-precision solves)
   DevMem d_Wb;         // bf16 high and low planes of W, rows of bf16_ldw(npw) (STH_MIXED_BF16)
@@ -259,6 +259,10 @@ class Context {
                 bool dots, int mode = OP_FP64);
   void apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
                   bool dots, bool bf16);
+  // v <- P_c v on the listed slots (FP64 GEMMs); with `dots`, partial
+  // Re<dot_in, v> per 64-row tile of the projected v into d_dots
+  void project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
+                 bool dots);
   void order_after(hipStream_t user);   // library stream waits for the user's stream
   void order_before(hipStream_t user);  // user's stream waits for the library stream
   void alloc_slots(System& s, int nslots);

@@ -302,8 +302,9 @@ void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st)
   STH_HIP_CHECK(hipGetLastError());
 }
 
-void launch_gemm_ah_b_bf16(const bz* Wb, int ldw, int M, VecSet<const z64> B, const int* slots,
-                           int ncols, int K, int kchunk, z32* part, hipStream_t st) {
+void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
+                           const int* slots, int ncols, int K, int kchunk, z32* part,
+                           hipStream_t st) {
   if (ncols <= 0 || M <= 0) return;
   if (ldw != bf16_ldw(K) || kchunk % 4 != 0) {
     set_error("bf16 GEMM: row pitch %d (want %d), K chunk %d (multiple of 4)", ldw, bf16_ldw(K),
@@ -312,13 +313,13 @@ void launch_gemm_ah_b_bf16(const bz* Wb, int ldw, int M, VecSet<const z64> B, co
   }
   const int nsplit = (K + kchunk - 1) / kchunk;
   dim3 grid((M + BT - 1) / BT, (ncols + BT - 1) / BT, nsplit);
-  hipLaunchKernelGGL(k_gemm_ah_b_bf16, grid, dim3(BTHR), 0, st, Wb, (long long)M * ldw, ldw, M, B,
+  hipLaunchKernelGGL(k_gemm_ah_b_bf16, grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
                      slots, ncols, K, kchunk, part);
   STH_HIP_CHECK(hipGetLastError());
 }
 
-void launch_gemm_a_c_bf16(const bz* Wb, int ldw, int M, const z32* C, VecSet<z64> Y,
-                          const int* slots, int ncols, int K, double s0,
+void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const z32* C,
+                          VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
                           VecSet<const z64> dot_in, double* dots, hipStream_t st) {
   if (ncols <= 0) return;
   if (ldw != bf16_ldw(K)) {
@@ -326,7 +327,7 @@ void launch_gemm_a_c_bf16(const bz* Wb, int ldw, int M, const z32* C, VecSet<z64
     throw Error(STH_E_INTERNAL);
   }
   dim3 grid(gemm_a_c_tiles(K), (ncols + BT - 1) / BT);
-  hipLaunchKernelGGL(k_gemm_a_c_bf16, grid, dim3(BTHR), 0, st, Wb, (long long)M * ldw, ldw, M, C,
+  hipLaunchKernelGGL(k_gemm_a_c_bf16, grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C,
                      Y, slots, ncols, K, s0, dot_in, dots);
   STH_HIP_CHECK(hipGetLastError());
 }
