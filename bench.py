@@ -96,6 +96,9 @@ def served(args):
     import paper_2203_05623_amd as P
 
     names = args.served_systems.split(",")
+    # the 432-band valence set-up of the 96^3 system takes minutes: one progress
+    # line per eigensolver iteration
+    os.environ.setdefault("STH_VERBOSE", "1")
     ctx = P.sth_create(device=0, max_slots=args.slots)
     systems = {}
     for name in names:
