@@ -66,9 +66,10 @@ enum { STH_PTR_HOST = 0, STH_PTR_DEVICE = 1 };
  * FFTs / H.psi inside the CG iterations with FP64 recurrences, residuals and
  * P_c; the returned solution always meets tol on the true FP64 residual
  * (paper, Section 4.3 and 5.1: FP32 FFTs and communication, FP64 elsewhere).
- * The projector / P_v GEMMs of that inner operator run on FP32 MFMA
+ * The Kleinman-Bylander GEMMs of that inner operator run on FP32 MFMA
  * (STH_MIXED) or on BF16 MFMA with FP32 accumulation, each FP32 operand split
- * into a bf16 high and low part (STH_MIXED_BF16). */
+ * into a bf16 high and low part (STH_MIXED_BF16); the P_c projection of every
+ * inner step stays on FP64 MFMA. */
 enum { STH_FP64 = 0, STH_MIXED = 1, STH_MIXED_BF16 = 2 };
 
 /* Per-solve status codes returned by sth_fetch_stats. */

@@ -658,9 +658,10 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
 // P_c K P_c.  The P_v part of p is never used: P_c (H - eps_v) maps it to zero
 // (Psi are eigenvectors of H), the step length takes <p, P_c q> (partials in
 // `dots` with `dot_in` = p), and x's P_v part is removed when the solve
-// retires.  The projection is FP64 also in mixed solves: an FP32 / BF16 one
-// would leave a P_v remainder in r that the directions never remove, stalling
-// the inner runs.  (The alternative, a shifted operator H - eps_v + alpha P_v
+// retires.  The projection is FP64 also in mixed solves: the FP32 / BF16
+// operator leaks a P_v part into q that must not reach r (the directions never
+// remove it), and what an FP32 projection would leave of it, ~1e-7 of q per
+// step, is scaled by the step length (1 / gap) before it lands in r.  (The alternative, a shifted operator H - eps_v + alpha P_v
 // on the whole sphere with K applied unprojected, needs no projection but about
 // 40% more iterations: K mixes P_v components into the CG's spectrum.)
 void Context::project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,

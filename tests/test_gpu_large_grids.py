@@ -12,8 +12,8 @@ kernels runs there.  Calls go through the C-ABI.
   tests/golden/make_response_cache.py from the oracle valence states of
   tests/golden/make_valence_cache.py (skipped when the caches are missing).
   The oracle's LOBPCG is run to residual 3e-9 at this size (it stalls near
-  2e-9); both sides take the same psi_0, and the shifted operator of the HIP
-  path differs from the projected one only at second order in that residual.
+  2e-9); both sides take the same psi_0 and solve the same projected
+  equation, so that residual enters both alike.
 """
 import functools
 import os
