@@ -420,9 +420,11 @@ def main():
     # dominant kernel phase and its roofline: the projector GEMMs against the
     # MFMA peak, the plane stage (FFT butterflies on the vector ALUs) against the
     # vector ALU peak with the nominal 5 N log2 N flops per transform, the other
-    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed.  The
-    # BF16 split GEMMs take the BF16 MFMA peak: their algorithmic (complex FP32)
-    # flops are issued as three BF16 products (hi hi, hi lo, lo hi)
+    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed.  In
+    # the BF16-mixed form a GEMM phase holds the KB products on BF16 MFMA (each
+    # algorithmic complex-FP32 flop issued as three BF16 products: hi hi, hi lo,
+    # lo hi) and the P_c projection on FP32 MFMA; its peak is the flop-weighted
+    # harmonic blend of BF16 / 3 and FP32 over the KB and valence row counts
     dom = max(prof, key=lambda k: prof[k][0])
     ms, nl, by, fl = prof[dom]
     kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
@@ -433,13 +435,14 @@ def main():
         if args.precision == "fp64":
             peak = MI355X_FP64_TFLOPS
         elif kind == "mfma" and args.precision == "mixed-bf16":
-            peak = MI355X_BF16_TFLOPS
+            w_kb = beta.shape[0] / (beta.shape[0] + cfg.nv)
+            peak = 1.0 / (w_kb * 3.0 / MI355X_BF16_TFLOPS + (1.0 - w_kb) / MI355X_FP32_TFLOPS)
         else:
             peak = MI355X_FP32_TFLOPS
         roof = {"bound": kind, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak,
                 "unit": "TFLOP/s"}
         if kind == "mfma" and args.precision == "mixed-bf16":
-            roof["mfma_products_per_flop"] = 3
+            roof["peak_blend"] = {"bf16_x3_rows": int(beta.shape[0]), "fp32_rows": int(cfg.nv)}
     roof["frac"] = roof["achieved"] / roof["peak"]
     # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (calibrated
     # on a 1 GiB copy) as a multiple of the algorithmic bytes, where measured

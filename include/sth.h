@@ -69,7 +69,7 @@ enum { STH_PTR_HOST = 0, STH_PTR_DEVICE = 1 };
  * The Kleinman-Bylander GEMMs of that inner operator run on FP32 MFMA
  * (STH_MIXED) or on BF16 MFMA with FP32 accumulation, each FP32 operand split
  * into a bf16 high and low part (STH_MIXED_BF16); the P_c projection of every
- * inner step stays on FP64 MFMA. */
+ * inner step runs on FP32 MFMA, that of every FP64 residual on FP64 MFMA. */
 enum { STH_FP64 = 0, STH_MIXED = 1, STH_MIXED_BF16 = 2 };
 
 /* Per-solve status codes returned by sth_fetch_stats. */

@@ -650,35 +650,53 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   prof_end(h, M * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
 }
 
-// Projection onto the conduction space, q <- q - Psi (Psi^H q), in FP64, on
-// the operator output q = (H - eps_v) p of every CG step and true residual.
-// The CG then runs on P_c (H - eps_v) P_c as the equation of Section 3 states
-// it: r stays in range(P_c), rho = <r, K r> = <r, P_c K r>, and the P_c part of
+// Projection onto the conduction space, q <- q - Psi (Psi^H q), on the
+// operator output q = (H - eps_v) p of every CG step and true residual.  The
+// CG then runs on P_c (H - eps_v) P_c as the equation of Section 3 states it:
+// r stays in range(P_c), rho = <r, K r> = <r, P_c K r>, and the P_c part of
 // p = K r + beta p evolves exactly as the direction of a CG preconditioned by
 // P_c K P_c.  The P_v part of p is never used: P_c (H - eps_v) maps it to zero
 // (Psi are eigenvectors of H), the step length takes <p, P_c q> (partials in
-// `dots` with `dot_in` = p), and x's P_v part is removed when the solve
-// retires.  The projection is FP64 also in mixed solves: the FP32 / BF16
-// operator leaks a P_v part into q that must not reach r (the directions never
-// remove it), and what an FP32 projection would leave of it, ~1e-7 of q per
-// step, is scaled by the step length (1 / gap) before it lands in r.  (The alternative, a shifted operator H - eps_v + alpha P_v
-// on the whole sphere with K applied unprojected, needs no projection but about
-// 40% more iterations: K mixes P_v components into the CG's spectrum.)
+// `dots` with `dot_in` = p), and x's P_v part is removed before every true
+// residual and when the solve retires.  The projection must not be skipped in
+// mixed solves: the FP32 / BF16 operator leaks a P_v part into q that the
+// directions would never remove from r, stalling the inner runs.  Their inner
+// steps project with FP32 GEMMs (mode != OP_FP64), which leaves ~1e-7 of
+// Psi^H q, a small vector since K is close to 1 where the valence states live;
+// FP64 steps and every true residual project in FP64.  (The alternative, a
+// shifted operator H - eps_v + alpha P_v on the whole sphere with K applied
+// unprojected, needs no projection but about 40% more iterations: K mixes P_v
+// components into the CG's spectrum.)
 void Context::project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
-                        bool dots) {
+                        bool dots, int mode) {
   const double vb = double(s.npw) * sizeof(z64);
   const double gf = 8.0 * s.nv * double(s.npw) * n;
+  double* dd = dots ? s.d_dots.as<double>() : nullptr;
   int h = prof_begin(PH_GEMM_AHB);
-  launch_gemm_ah_b(s.W(), s.npw, s.nv, {v.base, v.stride}, dl, n, s.npw, s.kchunk,
-                   s.d_part.as<z64>(), st_);
-  prof_end(h, s.nv * vb + n * vb, gf);
-  h = prof_begin(PH_REDUCE);
-  launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.nv, nullptr, -1.0, s.d_C.as<z64>(), st_);
-  prof_end(h, (s.nsplit + 1.0) * n * s.nv * sizeof(z64), 0.0);
-  h = prof_begin(PH_GEMM_AC);
-  launch_gemm_a_c(s.W(), s.npw, s.nv, s.d_C.as<z64>(), v, dl, n, s.npw, 1.0, dot_in,
-                  dots ? s.d_dots.as<double>() : nullptr, st_);
-  prof_end(h, s.nv * vb + n * vb * (dots ? 3.0 : 2.0), gf);
+  if (mode == OP_FP64) {
+    launch_gemm_ah_b(s.W(), s.npw, s.nv, {v.base, v.stride}, dl, n, s.npw, s.kchunk,
+                     s.d_part.as<z64>(), st_);
+    prof_end(h, s.nv * vb + n * vb, gf);
+    h = prof_begin(PH_REDUCE);
+    launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.nv, nullptr, -1.0, s.d_C.as<z64>(),
+                        st_);
+    prof_end(h, (s.nsplit + 1.0) * n * s.nv * sizeof(z64), 0.0);
+    h = prof_begin(PH_GEMM_AC);
+    launch_gemm_a_c(s.W(), s.npw, s.nv, s.d_C.as<z64>(), v, dl, n, s.npw, 1.0, dot_in, dd, st_);
+    prof_end(h, s.nv * vb + n * vb * (dots ? 3.0 : 2.0), gf);
+  } else {
+    z32* part = reinterpret_cast<z32*>(s.d_part.as<z64>());
+    z32* C = reinterpret_cast<z32*>(s.d_C.as<z64>());
+    launch_gemm_ah_b(s.d_W32.as<z32>(), s.npw, s.nv, {v.base, v.stride}, dl, n, s.npw, s.kchunk,
+                     part, st_);
+    prof_end(h, s.nv * vb / 2 + n * vb, gf);
+    h = prof_begin(PH_REDUCE);
+    launch_reduce_parts(part, s.nsplit, n, s.nv, nullptr, -1.0, C, st_);
+    prof_end(h, (s.nsplit + 1.0) * n * s.nv * sizeof(z32), 0.0);
+    h = prof_begin(PH_GEMM_AC);
+    launch_gemm_a_c(s.d_W32.as<z32>(), s.npw, s.nv, C, v, dl, n, s.npw, 1.0, dot_in, dd, st_);
+    prof_end(h, s.nv * vb / 2 + n * vb * (dots ? 3.0 : 2.0), gf);
+  }
 }
 
 // ------------------------------------------------------------------ profiling
@@ -1152,7 +1170,7 @@ void Context::refill(System& s) {
 void Context::cg_step(System& s, const int* dl, int n, int mode) {
   const double vb = double(s.npw) * sizeof(z64);
   apply_op(s, s.cvec(s.d_p), s.vec(s.d_q), dl, n, false, mode);
-  project_c(s, s.vec(s.d_q), dl, n, s.cvec(s.d_p), true);
+  project_c(s, s.vec(s.d_q), dl, n, s.cvec(s.d_p), true, mode);
   const int h = prof_begin(PH_CG);
   launch_cg_alpha(s.d_dots.as<double>(), s.ntile, dl, n, s.ss, st_);
   launch_cg_update_xr(s.g, s.vec(s.d_x), s.vec(s.d_r), s.cvec(s.d_p), s.cvec(s.d_q), dl, n, s.ss,
@@ -1230,9 +1248,9 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
     // (H - eps) Psi = Psi (Lambda - eps) only as far as the valence states
     // are eigenvectors, so they could bias the check
     int* dl = upload_list(s, check);
-    project_c(s, s.vec(s.d_x), dl, n, {nullptr, 0}, false);
+    project_c(s, s.vec(s.d_x), dl, n, {nullptr, 0}, false, OP_FP64);
     apply_op(s, s.cvec(s.d_x), s.vec(s.d_q), dl, n, false);
-    project_c(s, s.vec(s.d_q), dl, n, {nullptr, 0}, false);
+    project_c(s, s.vec(s.d_q), dl, n, {nullptr, 0}, false, OP_FP64);
     launch_cg_true_resid(s.g, s.cvec(s.d_b), s.cvec(s.d_q), s.vec(s.d_r), dl, n, s.ss.ekin,
                          s.d_part2.as<double>(), st_);
     launch_cg_check_true(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);

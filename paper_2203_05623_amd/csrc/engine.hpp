@@ -259,10 +259,10 @@ class Context {
                 bool dots, int mode = OP_FP64);
   void apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const int* dl, int n,
                   bool dots, bool bf16);
-  // v <- P_c v on the listed slots (FP64 GEMMs); with `dots`, partial
-  // Re<dot_in, v> per 64-row tile of the projected v into d_dots
+  // v <- P_c v on the listed slots (FP64 GEMMs for OP_FP64, FP32 otherwise);
+  // with `dots`, partial Re<dot_in, v> per 64-row tile of the projected v into d_dots
   void project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
-                 bool dots);
+                 bool dots, int mode);
   void order_after(hipStream_t user);   // library stream waits for the user's stream
   void order_before(hipStream_t user);  // user's stream waits for the library stream
   void alloc_slots(System& s, int nslots);
