@@ -221,11 +221,75 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
-          acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
+          if constexpr (sizeof(T) == 4) {   // transposed tile: column index in the rows
+            accr[x][y] = Mfma<T>::op(br[y], a[x], accr[x][y]);
+            acci[x][y] = Mfma<T>::op(bi[y], a[x], acci[x][y]);
+          } else {
+            accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
+            acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
+          }
         }
     }
     __syncthreads();
+  }
+  if constexpr (sizeof(T) == 4) {
+    // FP32: the tile is held transposed, D[n][g] with n = 4 (l / 16) + v and
+    // g = l % 16, so that one store instruction writes 16 consecutive g of each
+    // of 4 columns (256 B runs) instead of 16 B pieces 64 B apart
+    double dsum[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = n0 + wn * 32 + y * 16 + 4 * kq + v;
+        if (n >= ncols) continue;
+        z64* yrow = Y.base + (long long)slots[n] * Y.stride;
+        const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int gg = g0 + wg * 32 + x * 16 + r16;
+          if (gg < K) {
+            z64 o = {double(accr[x][y][v]), double(acci[x][y][v])};
+            if (s0 != 0.0) {
+              const z64 yo = yrow[gg];
+              o.x += s0 * yo.x;
+              o.y += s0 * yo.y;
+            }
+            yrow[gg] = o;
+            if (drow) {
+              const z64 d = drow[gg];
+              dsum[y][v] += d.x * o.x + d.y * o.y;
+            }
+          }
+        }
+      }
+    if (!dots) return;
+    // sum over the 16 lanes that share a column, then over the two g halves
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) dsum[y][v] += __shfl_xor(dsum[y][v], o);
+    double* redf = &red[0][0];   // [GT] column sums of the wg == 1 half
+    if (wg == 1 && r16 == 0) {
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) redf[wn * 32 + y * 16 + 4 * kq + v] = dsum[y][v];
+    }
+    __syncthreads();
+    if (wg == 0 && r16 == 0) {
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = wn * 32 + y * 16 + 4 * kq + v;
+          const int n = n0 + c;
+          if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y][v] + redf[c];
+        }
+    }
+    return;
   }
   double dsum[2] = {0.0, 0.0};
 #pragma unroll
