@@ -122,6 +122,8 @@ typedef struct {
   long long op_applications_fp32; /* of which with the FP32 inner operator (mixed forms) */
   long long graph_replays;  /* hipGraph replays of captured CG iterations on the ticket's
                                system so far (steady state with every slot busy) */
+  int system_id;            /* system the ticket was submitted to */
+  int npert, nband;         /* shape of the request: outputs are [npert][...] */
 } sth_ticket_info;
 
 /* Creates a context on cfg->device (cfg may be NULL for defaults).  Starts the
@@ -163,6 +165,7 @@ typedef struct {
                                                  exceeds the LDS) */
   int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"): 0
                                                  workgroup form, 1 wave form */
+  int n;                              /* FFT grid points per axis */
 } sth_system_info;
 sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 

@@ -52,7 +52,8 @@ class sth_ticket_info(C.Structure):
                 ("n_converged", C.c_int), ("max_rel_resid", C.c_double),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
                 ("cg_iterations", C.c_longlong), ("op_applications", C.c_longlong),
-                ("op_applications_fp32", C.c_longlong), ("graph_replays", C.c_longlong)]
+                ("op_applications_fp32", C.c_longlong), ("graph_replays", C.c_longlong),
+                ("system_id", C.c_int), ("npert", C.c_int), ("nband", C.c_int)]
 
 
 class sth_system_info(C.Structure):
@@ -61,7 +62,7 @@ class sth_system_info(C.Structure):
                 ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 32),
                 ("tuned_from_cache", C.c_int), ("plane_kernel_fp64", C.c_int),
                 ("plane_kernel_fp32", C.c_int), ("zfft_kernel_fp64", C.c_int),
-                ("zfft_kernel_fp32", C.c_int)]
+                ("zfft_kernel_fp32", C.c_int), ("n", C.c_int)]
 
 
 class SthError(RuntimeError):
@@ -128,17 +129,49 @@ def _is_torch(a):
     return type(a).__module__.startswith("torch")
 
 
-def _ptr(a, dtype):
-    """(pointer, ptr_kind, keepalive) of a numpy array or a torch tensor."""
+_TORCH_DTYPES = {np.dtype(np.float64): "float64", np.dtype(np.complex128): "complex128",
+                 np.dtype(np.int32): "int32"}
+
+
+def _ptr(a, dtype, count=None, name="array", out=False):
+    """(pointer, ptr_kind, keepalive) of a numpy array or a torch tensor.
+
+    The library takes no lengths, so every array is checked here: a torch
+    tensor (host or device) must have exactly `dtype`, be contiguous and hold
+    `count` elements (complex128 counted as complex numbers); a numpy input is
+    converted to a contiguous `dtype` copy, a numpy output must already be one
+    (a copy would lose the result).  ValueError otherwise."""
     if a is None:
         return None, STH_PTR_HOST, None
+    dt = np.dtype(dtype)
     if _is_torch(a):
+        want = _TORCH_DTYPES[dt]
+        got = str(a.dtype).replace("torch.", "")
+        # complex data may arrive as a float64 view of (re, im) pairs
+        if got == "float64" and want == "complex128":
+            n = a.numel() // 2
+        elif got != want:
+            raise ValueError(f"{name}: tensor dtype {got}, expected {want}")
+        else:
+            n = a.numel()
         if not a.is_contiguous():
-            raise ValueError("tensor must be contiguous")
+            raise ValueError(f"{name}: tensor must be contiguous")
+        if count is not None and n != count:
+            raise ValueError(f"{name}: {n} elements, expected {count}")
         if a.is_cuda:
             return a.data_ptr(), STH_PTR_DEVICE, a
         a = a.numpy()
-    arr = np.ascontiguousarray(a, dtype=dtype)
+        if got == "float64" and want == "complex128":
+            a = a.view(np.complex128)
+    if out:
+        if not (isinstance(a, np.ndarray) and a.dtype == dt and a.flags.c_contiguous
+                and a.flags.writeable):
+            raise ValueError(f"{name}: output must be a writeable C-contiguous {dt} array")
+        arr = a
+    else:
+        arr = np.ascontiguousarray(a, dtype=dt)
+    if count is not None and arr.size != count:
+        raise ValueError(f"{name}: {arr.size} elements, expected {count}")
     return arr.ctypes.data, STH_PTR_HOST, arr
 
 
@@ -147,13 +180,6 @@ def _stream(a=None):
         import torch
         return torch.cuda.current_stream(a.device).cuda_stream
     return None
-
-
-def _c128_as_f64(a):
-    if _is_torch(a):
-        import torch
-        return torch.view_as_real(a) if a.is_complex() else a
-    return np.ascontiguousarray(a, dtype=np.complex128)
 
 
 # ------------------------------------------------------------------ C-ABI functions
@@ -171,11 +197,12 @@ def sth_destroy(ctx):
 def _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor):
     miller = np.ascontiguousarray(miller, dtype=np.int32).reshape(-1, 3)
     npw = len(miller)
+    n = int(n)
     keep = [miller]
     kinds = set()
 
-    def p(a, dt):
-        ptr, kind, k = _ptr(a, dt)
+    def p(a, dt, count, name):
+        ptr, kind, k = _ptr(a, dt, count, name)
         keep.append(k)
         if a is not None:
             kinds.add(kind)
@@ -184,12 +211,17 @@ def _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor):
     nproj = 0 if beta is None else int(beta.shape[0])
     nv = 0 if psi_v is None else int(psi_v.shape[0])
     d = sth_system_desc(
-        L=float(L), n=int(n), npw=npw, miller=miller.ctypes.data_as(C.POINTER(C.c_int32)),
-        vloc_r=p(vloc_r, np.float64), nproj=nproj,
-        beta=p(None if beta is None else _c128_as_f64(beta), np.complex128),
-        dij=p(dij, np.float64), nv=nv,
-        psi_v=p(None if psi_v is None else _c128_as_f64(psi_v), np.complex128),
-        eps_v=p(eps_v, np.float64), spin_factor=float(spin_factor), ptr_kind=STH_PTR_HOST)
+        L=float(L), n=n, npw=npw, miller=miller.ctypes.data_as(C.POINTER(C.c_int32)),
+        vloc_r=p(vloc_r, np.float64, n ** 3, "vloc_r"), nproj=nproj,
+        beta=p(beta, np.complex128, nproj * npw, "beta"),
+        dij=p(dij, np.float64, nproj, "dij"), nv=nv,
+        psi_v=p(psi_v, np.complex128, nv * npw, "psi_v"),
+        eps_v=p(eps_v, np.float64, nv, "eps_v"), spin_factor=float(spin_factor),
+        ptr_kind=STH_PTR_HOST)
+    if nproj and dij is None:
+        raise ValueError("dij is required with beta")
+    if nv and eps_v is None:
+        raise ValueError("eps_v is required with psi_v")
     if len(kinds) > 1:
         raise ValueError("system arrays must all be host arrays or all device tensors")
     d.ptr_kind = kinds.pop() if kinds else STH_PTR_HOST
@@ -210,11 +242,12 @@ def sth_release_system(ctx, system_id):
 
 def sth_apply_h(ctx, system_id, c, out=None):
     """H c for c complex [nvec, npw] (numpy or torch); returns out."""
-    nvec = c.shape[0]
+    npw = sth_system_info_get(ctx, system_id)["npw"]
+    nvec = int(c.shape[0])
     if out is None:
-        out = np.empty_like(np.asarray(c, dtype=np.complex128)) if not _is_torch(c) else c.clone()
-    pin, kin, k1 = _ptr(_c128_as_f64(c), np.complex128)
-    pout, kout, k2 = _ptr(_c128_as_f64(out), np.complex128)
+        out = np.empty((nvec, npw), np.complex128) if not _is_torch(c) else c.clone()
+    pin, kin, k1 = _ptr(c, np.complex128, nvec * npw, "c")
+    pout, kout, k2 = _ptr(out, np.complex128, nvec * npw, "out", out=True)
     if kin != kout:
         raise ValueError("in and out must live on the same side")
     _check(lib().sth_apply_h(ctx, system_id, nvec, pin, pout, kin, _stream(c)))
@@ -237,9 +270,10 @@ def sth_valence(ctx, L, n, miller, vloc_r, beta, dij, nbands, tol=1e-10, maxit=0
 
 def sth_submit_solves(ctx, system_id, dv_r, bands, tol=1e-10, maxit=0, precision=STH_FP64,
                       want_dpsi=False):
+    n = sth_system_info_get(ctx, system_id)["n"]
     npert = int(dv_r.shape[0])
-    bands = np.ascontiguousarray(bands, dtype=np.int32)
-    pdv, kind, keep = _ptr(dv_r, np.float64)
+    bands = np.ascontiguousarray(bands, dtype=np.int32).reshape(-1)
+    pdv, kind, keep = _ptr(dv_r, np.float64, npert * n ** 3, "dv_r")
     opts = sth_solve_opts(float(tol), int(maxit), int(precision), int(bool(want_dpsi)))
     t = C.c_uint64()
     _check(lib().sth_submit_solves(ctx, system_id, npert, pdv, len(bands),
@@ -263,24 +297,32 @@ def sth_wait(ctx, ticket, timeout_s=1e9):
     return True
 
 
+def _ticket_shape(ctx, ticket):
+    info = sth_poll(ctx, ticket)
+    sysinfo = sth_system_info_get(ctx, info["system_id"])
+    return info["npert"], info["nband"], sysinfo["n"], sysinfo["npw"]
+
+
 def sth_fetch_drho(ctx, ticket, out):
-    p, kind, keep = _ptr(out, np.float64)
-    if keep is not out and not _is_torch(out):
-        raise ValueError("out must be a C-contiguous float64 array")
+    npert, _, n, _ = _ticket_shape(ctx, ticket)
+    p, kind, keep = _ptr(out, np.float64, npert * n ** 3, "drho", out=True)
     _check(lib().sth_fetch_drho(ctx, ticket, p, kind, _stream(out)))
     return out
 
 
 def sth_fetch_dpsi(ctx, ticket, out):
-    o = _c128_as_f64(out)
-    p, kind, keep = _ptr(o, np.complex128)
-    if not _is_torch(out) and keep is not out:
-        raise ValueError("out must be a C-contiguous complex128 array")
+    npert, nband, _, npw = _ticket_shape(ctx, ticket)
+    p, kind, keep = _ptr(out, np.complex128, npert * nband * npw, "dpsi", out=True)
     _check(lib().sth_fetch_dpsi(ctx, ticket, p, kind, _stream(out)))
     return out
 
 
-def sth_fetch_stats(ctx, ticket, n):
+def sth_fetch_stats(ctx, ticket, n=None):
+    """Per-solve (iterations, true relative residual, status, latency), each [npert * nband]."""
+    npert, nband, _, _ = _ticket_shape(ctx, ticket)
+    if n is not None and n != npert * nband:
+        raise ValueError(f"ticket holds {npert * nband} solves, not {n}")
+    n = npert * nband
     iters = np.empty(n, np.int32)
     resid = np.empty(n)
     status = np.empty(n, np.int32)
@@ -290,7 +332,11 @@ def sth_fetch_stats(ctx, ticket, n):
     return iters, resid, status, lat
 
 
-def sth_chi0_block(ctx, ticket, npert):
+def sth_chi0_block(ctx, ticket, npert=None):
+    np_, _, _, _ = _ticket_shape(ctx, ticket)
+    if npert is not None and npert != np_:
+        raise ValueError(f"ticket holds {np_} perturbations, not {npert}")
+    npert = np_
     M = np.empty((npert, npert))
     S = np.empty((npert, npert))
     lam = np.empty(npert)
@@ -306,7 +352,8 @@ def sth_lanczos(ctx, system_id, band, phi, nsteps):
     """Lanczos chains of orbital `band` for the real grids phi [nphi, n, n, n]:
     (alpha, beta, d [nphi, nsteps], U [nphi, nsteps, nsteps], braket [nphi, nphi, nsteps])."""
     nphi = int(phi.shape[0])
-    p, kind, keep = _ptr(phi, np.float64)
+    n = sth_system_info_get(ctx, system_id)["n"]
+    p, kind, keep = _ptr(phi, np.float64, nphi * n ** 3, "phi")
     alpha = np.empty((nphi, nsteps))
     beta = np.empty((nphi, nsteps))
     d = np.empty((nphi, nsteps))
@@ -323,6 +370,8 @@ def sth_pdep(ctx, system_id, n, npdep, nmax=0, tol=1e-6, maxit=100, solve_tol=1e
              precision=STH_FP64, want_vectors=True):
     """(eigenvalues [npdep], eigenvectors [npdep, n, n, n] or None, iterations, max residual);
     n is the system's grid size (shape of the vectors); nmax 0 means 4 npdep."""
+    if n != sth_system_info_get(ctx, system_id)["n"]:
+        raise ValueError("n must be the system's grid size")
     eig = np.empty(npdep)
     vec = np.empty((npdep, n, n, n)) if want_vectors else None
     its = C.c_int()

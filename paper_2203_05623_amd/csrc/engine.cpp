@@ -916,6 +916,9 @@ void Context::poll(uint64_t t, sth_ticket_info* info) {
   info->op_applications_fp32 = r->op32_apps;
   const auto sit = systems_.find(r->sys_id);   // the system may have been released
   info->graph_replays = sit != systems_.end() ? sit->second->graph_replays : 0;
+  info->system_id = r->sys_id;
+  info->npert = r->npert;
+  info->nband = r->nband;
 }
 
 bool Context::wait(uint64_t t, double timeout) {
@@ -1259,6 +1262,24 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
       std::lock_guard<std::mutex> lk(mu_);
       for (int slot : check) s.slots[slot].req->op_apps += 1;
     }
+    read_state();
+  }
+  // solves that stopped inside the recurrence (maxit in the beta step, breakdown)
+  // report the true FP64 residual of their last iterate, not the recursive one
+  // (for mixed solves that would be the residual of the inner operator)
+  std::vector<int> stopped;
+  for (int i = 0; i < s.nslots; ++i)
+    if (s.slots[i].req && (h_status[i] == SLOT_MAXIT || h_status[i] == SLOT_BREAKDOWN))
+      stopped.push_back(i);
+  if (!stopped.empty()) {
+    const int n = int(stopped.size());
+    int* dl = upload_list(s, stopped);
+    project_c(s, s.vec(s.d_x), dl, n, {nullptr, 0}, false, OP_FP64);
+    apply_op(s, s.cvec(s.d_x), s.vec(s.d_q), dl, n, false);
+    project_c(s, s.vec(s.d_q), dl, n, {nullptr, 0}, false, OP_FP64);
+    launch_cg_true_resid(s.g, s.cvec(s.d_b), s.cvec(s.d_q), s.vec(s.d_r), dl, n, s.ss.ekin,
+                         s.d_part2.as<double>(), st_);
+    launch_cg_check_true(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_, true);
     read_state();
   }
   std::vector<int> fin;

@@ -245,9 +245,11 @@ __global__ __launch_bounds__(CTHR) void k_cg_true_resid(GridDev g, VecSet<const 
 }
 
 // After a true residual: DONE if it meets tol, else restart the recurrence on it
-// (rho = <r, K r>, beta = 0, so the next p-update sets p = K r).
+// (rho = <r, K r>, beta = 0, so the next p-update sets p = K r).  With
+// final_only the slot has already stopped (MAXIT or BREAKDOWN): only its
+// residual norm is replaced by the true one.
 __global__ void k_cg_check_true(const double* part2, int nchunk, const int* slots, int ncols,
-                                SlotState s) {
+                                SlotState s, int final_only) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
   const int slot = slots[c];
@@ -258,6 +260,10 @@ __global__ void k_cg_check_true(const double* part2, int nchunk, const int* slot
   }
   s.rnorm2[slot] = rr;
   s.beta[slot] = 0.0;
+  if (final_only) {
+    if (rr != rr) s.status[slot] = SLOT_NAN;
+    return;
+  }
   if (rr != rr) {
     s.status[slot] = SLOT_NAN;
   } else if (rr <= s.tol[slot] * s.tol[slot] * s.bnorm2[slot]) {
@@ -425,10 +431,10 @@ void launch_cg_true_resid(const GridDev& g, VecSet<const z64> b, VecSet<const z6
 }
 
 void launch_cg_check_true(const double* part2, int nchunk, const int* slots, int ncols,
-                          SlotState s, hipStream_t st) {
+                          SlotState s, hipStream_t st, bool final_only) {
   if (ncols <= 0) return;
   hipLaunchKernelGGL(k_cg_check_true, scalar_grid(ncols), dim3(128), 0, st, part2, nchunk, slots,
-                     ncols, s);
+                     ncols, s, int(final_only));
   STH_HIP_CHECK(hipGetLastError());
 }
 

@@ -169,9 +169,10 @@ void launch_cg_update_p(const GridDev& g, VecSet<const z64> r, VecSet<z64> p, co
 void launch_cg_true_resid(const GridDev& g, VecSet<const z64> b, VecSet<const z64> q,
                           VecSet<z64> r, const int* slots, int ncols, const double* ekin_slot,
                           double* part2, hipStream_t st);
-// after a true residual: DONE if ||r|| <= tol ||b||, else restart (rho = <r, K r>, beta = 0)
+// after a true residual: DONE if ||r|| <= tol ||b||, else restart (rho = <r, K r>, beta = 0);
+// final_only: only store the true ||r||^2 of a slot that has already stopped
 void launch_cg_check_true(const double* part2, int nchunk, const int* slots, int ncols,
-                          SlotState s, hipStream_t st);
+                          SlotState s, hipStream_t st, bool final_only = false);
 
 // ---- small helpers ----
 void launch_copy_vecs(VecSet<const z64> src, VecSet<z64> dst, const int* slots_src,

@@ -209,6 +209,7 @@ void Context::system_info(int id, sth_system_info* info) {
   info->gemm_kchunk = s.kchunk;
   for (int i = 0; i < 32; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
+  info->n = s.N;
 }
 
 }  // namespace sth

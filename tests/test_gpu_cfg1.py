@@ -158,6 +158,35 @@ def test_solve_status_reports_maxit(sth, cfg1, sys1):
     P.sth_release_ticket(ctx, t)
 
 
+@pytest.mark.parametrize("form", ["mixed", "mixed-bf16"])
+def test_maxit_reports_true_fp64_residual(sth, cfg1, sys1, form):
+    """A mixed-precision solve stopped by maxit inside the recurrence reports the
+    true FP64 residual ||b - A x|| / ||b|| of the iterate it returns (recomputed
+    here with the oracle's dense operator), not the recursive residual of the
+    FP32 / BF16 inner operator."""
+    P, ctx = sth
+    cfg, s, H, eps, Psi = cfg1
+    prec = {"mixed": P.STH_MIXED, "mixed-bf16": P.STH_MIXED_BF16}[form]
+    dv = workloads.dv_block(cfg, range(2))
+    t = P.sth_submit_solves(ctx, sys1, dv, np.arange(NV), tol=1e-12, maxit=4, precision=prec,
+                            want_dpsi=True)
+    assert P.sth_wait(ctx, t, 60.0)
+    iters, resid, status, lat = P.sth_fetch_stats(ctx, t)
+    assert np.all(status == P._lib.SOLVE_MAXIT)
+    dpsi = np.empty((2, NV, s.npw), np.complex128)
+    P.sth_fetch_dpsi(ctx, t, dpsi)
+    n = s.npw
+    Pc = np.eye(n) - Psi.T @ Psi.conj()
+    for j in range(2):
+        for v in range(NV):
+            b = oracle.rhs(s, Psi, v, dv[j])
+            A = Pc @ (H - eps[v] * np.eye(n)) @ Pc
+            true = np.linalg.norm(b - A @ dpsi[j, v]) / np.linalg.norm(b)
+            k = j * NV + v
+            assert abs(resid[k] - true) <= 1e-6 * true, (j, v, resid[k], true)
+    P.sth_release_ticket(ctx, t)
+
+
 def test_invalid_arguments_are_errors(sth, cfg1, sys1):
     P, ctx = sth
     cfg, s, H, eps, Psi = cfg1
