@@ -3,14 +3,18 @@
 A step is one pass of the whole hot path over one request: the right-hand
 sides -P_c dV_j psi_v, the batched PCG solves of every (perturbation, band)
 pair to a true relative residual of 1e-8, the density responses dn_j and the
-chi0 block Rayleigh-Ritz.  Workload (default): the 64-atom synthetic supercell
-on a 72^3 grid (22,575 plane waves, 128 valence bands from the device LOBPCG,
-4 KB projectors per atom), 256 perturbations = 32,768 solves per step.
+chi0 block Rayleigh-Ritz.  Workload (default): the 512-atom synthetic cell on
+a 144^3 grid (187,511 plane waves, 1024 valence bands from the device
+eigensolver, 2048 KB projectors), 4 of its 64 perturbations per step = 4,096
+solves, in FP64 and (the `compare` object) BF16-mixed precision, timed alike;
+then the 64-atom crystal on a 72^3 grid (256 perturbations x 128 bands =
+32,768 solves per step) the same way (the `extra` object).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5] [--npert 4]
 
 Prints one JSON line.  The CPU baseline is the oracle (plain FP64 NumPy PCG)
-timed on a bounded sample of the same solves, run before the GPU is touched.
+timed on a bounded sample of the same solves by worker processes forked
+before the GPU is touched.
 """
 from __future__ import annotations
 
@@ -45,45 +49,114 @@ PRECISIONS = {"fp64": lambda P: P.STH_FP64, "mixed": lambda P: P.STH_MIXED,
 
 
 # ---------------------------------------------------------------- CPU baseline (oracle)
-def _oracle_worker(args):
+# The oracle runs in a process pool forked before the GPU is touched.  One
+# worker builds the oracle's system and stores its arrays as .npy files in a
+# scratch directory while the parent computes the valence states on the GPU;
+# the parent stores those states next to them (the oracle has no eigensolver
+# that finishes at these sizes); every worker checks its band's residual
+# ||H psi_v - eps_v psi_v|| with the oracle's H before timing its solves.
+_ORC = {}
+
+
+def _oracle_env():
     os.environ["OMP_NUM_THREADS"] = "1"
-    name, cache, pairs, tol = args
-    import oracle
     import oracle.hamiltonian as oh
     oh._WORKERS = 1
-    d = np.load(cache)
-    cfg = workloads.get_config(name)
-    s = oracle.build_system(name)
-    eps, Psi = d["eps"][:cfg.nv], d["psi"][:cfg.nv]
-    its = 0
-    for j, v in pairs:
-        b = oracle.rhs(s, Psi, v, workloads.dv_r(cfg, j))
-        _, it, rel, st = oracle.pcg_solve(s, Psi, eps, v, b, tol=tol)
-        its += it
-    return its
 
 
-def cpu_baseline(name: str, tol: float, nsample: int):
-    """Oracle solves/s on a bounded sample, process pool of single-threaded workers."""
-    cfg = workloads.get_config(name)
-    cache = os.path.join(ROOT, "tests", "_cache", f"{name}_seed{cfg.seed_kb}_valence.npz")
-    if not os.path.exists(cache):
-        return None
-    import multiprocessing as mp
-    cores = min(16, os.cpu_count() or 1)
-    nsample = max(cores, nsample - nsample % cores)
-    rng = np.random.default_rng(3)
-    pairs = [(int(rng.integers(cfg.npert)), int(rng.integers(cfg.nv))) for _ in range(nsample)]
-    chunks = [(name, cache, pairs[i::cores], tol) for i in range(cores)]
-    ctx = mp.get_context("fork")
+def _oracle_prepare(name, scratch):
+    _oracle_env()
+    import oracle
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        its = sum(pool.map(_oracle_worker, chunks))
-    dt = time.perf_counter() - t0
-    return {"value": nsample / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nsample} random (perturbation, band) solves of {name} at tol {tol:g}, "
-                      f"{its} CG iterations in total, {dt:.1f} s wall on {cores} worker processes "
-                      f"(one thread each), valence states from the oracle cache"}
+    s = oracle.build_system(name)
+    for k in ("miller", "vloc_r", "beta", "dij"):
+        np.save(os.path.join(scratch, k + ".npy"), getattr(s, k))
+    return time.perf_counter() - t0
+
+
+def _oracle_sample(args):
+    """Right-hand side plus PCG of (j, v) on the oracle, at most `maxit` iterations."""
+    name, scratch, j, v, tol, maxit = args
+    _oracle_env()
+    import oracle
+    cfg = workloads.get_config(name)
+    if "sys" not in _ORC:
+        ld = lambda k: np.load(os.path.join(scratch, k + ".npy"), mmap_mode="r")  # noqa: E731
+        _ORC["sys"] = oracle.System(L=cfg.L, N=cfg.N, miller=np.asarray(ld("miller")),
+                                    vloc_r=np.asarray(ld("vloc_r")), beta=ld("beta"),
+                                    dij=np.asarray(ld("dij")))
+        _ORC["eps"], _ORC["psi"] = np.load(os.path.join(scratch, "eps.npy")), ld("psi")
+    s, eps, psi = _ORC["sys"], _ORC["eps"], _ORC["psi"]
+    hv = oracle.apply_H(s, np.asarray(psi[v])[None])[0]
+    vres = float(np.linalg.norm(hv - eps[v] * psi[v]))
+    t0 = time.perf_counter()
+    b = oracle.rhs(s, psi, v, workloads.dv_r(cfg, j))
+    t1 = time.perf_counter()
+    _, it, rel, st = oracle.pcg_solve(s, psi, eps, v, b, tol=tol, maxit=maxit)
+    t2 = time.perf_counter()
+    return {"rhs_s": t1 - t0, "pcg_s": t2 - t1, "iters": it, "status": st, "valence_res": vres}
+
+
+class OraclePool:
+    """Single-threaded oracle workers, forked at construction (before any GPU call)."""
+
+    def __init__(self, name, cores):
+        import multiprocessing as mp
+        import tempfile
+        self.name, self.cores = name, cores
+        base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+        self.scratch = tempfile.mkdtemp(prefix="sth_oracle_", dir=base)
+        self.pool = mp.get_context("fork").Pool(cores)
+        self.prep = self.pool.apply_async(_oracle_prepare, (name, self.scratch))
+
+    def set_valence(self, eps, psi):
+        np.save(os.path.join(self.scratch, "eps.npy"), np.asarray(eps))
+        np.save(os.path.join(self.scratch, "psi.npy"), np.asarray(psi))
+
+    def run(self, npert, nv, tol, nsample, maxit, gpu_mean_iters):
+        build_s = self.prep.get()
+        rng = np.random.default_rng(3)
+        pairs = [(int(rng.integers(npert)), int(rng.integers(nv))) for _ in range(nsample)]
+        t0 = time.perf_counter()
+        res = self.pool.map(_oracle_sample, [(self.name, self.scratch, j, v, tol, maxit)
+                                             for j, v in pairs], chunksize=1)
+        wall = time.perf_counter() - t0
+        worst_vres = max(r["valence_res"] for r in res)
+        if not worst_vres <= 1e-9:
+            raise RuntimeError(f"valence states fail the oracle's residual check ({worst_vres:.2e})")
+        its = sum(r["iters"] for r in res)
+        full = all(r["status"] == 0 for r in res)
+        t_rhs = sum(r["rhs_s"] for r in res) / len(res)
+        t_it = sum(r["pcg_s"] for r in res) / its
+        if full:   # whole solves: time per solve as measured
+            per_solve = t_rhs + t_it * its / len(res)
+            how = f"{len(res)} whole solves ({its} PCG iterations)"
+        else:      # bounded solves: per-iteration time x the GPU run's mean iteration count
+            per_solve = t_rhs + t_it * gpu_mean_iters
+            how = (f"{len(res)} solves cut at {maxit} PCG iterations each (right-hand side "
+                   f"{t_rhs:.2f} s, {t_it:.2f} s per iteration), extrapolated to "
+                   f"{gpu_mean_iters:.1f} iterations per solve (the GPU run's mean)")
+        cpu_model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        return {"value": self.cores / per_solve, "unit": "solves/s", "cores": self.cores,
+                "kind": "oracle", "value_1core": 1.0 / per_solve,
+                "cpu_model": cpu_model, "os_cpu_count": os.cpu_count(),
+                "sample": f"{how} of random (perturbation, band) pairs of {self.name} at tol "
+                          f"{tol:g}, {wall:.1f} s wall on {self.cores} worker processes (one "
+                          f"thread each); valence states from the GPU run, residual "
+                          f"||H psi - eps psi|| <= {worst_vres:.1e} on the oracle's H; oracle "
+                          f"system set-up {build_s:.0f} s not timed"}
+
+    def close(self):
+        import shutil
+        self.pool.terminate()
+        shutil.rmtree(self.scratch, ignore_errors=True)
 
 
 # ---------------------------------------------------------------- served mode
@@ -261,25 +334,173 @@ def lanczos_run(args):
 
 
 # ---------------------------------------------------------------- GPU run
+# perturbations per step of the default workloads: the 512-atom share runs 4 of
+# its 64 perturbations x 1024 bands per step (4,096 solves, two fills of the
+# 2048-slot pool) so that a step stays near half a minute in FP64; the 64-atom
+# crystal runs all 256 x 128
+DEFAULT_NPERT = {"cfg5": 4}
+
+
+def _system(cfg):
+    miller = workloads.miller_sphere(cfg.M2)
+    return (miller, workloads.vloc_r(cfg), workloads.beta_projectors(cfg, miller),
+            workloads.dij(cfg))
+
+
+def _peak(kind, precision, nproj, nv):
+    """Peak of a phase: FP64 / FP32 vector ALU or MFMA; for the BF16-mixed GEMM
+    phases the flop-weighted harmonic blend of BF16 / 3 (KB rows, three bf16
+    products per complex-FP32 flop) and FP32 (valence rows)."""
+    if precision == "fp64":
+        return MI355X_FP64_TFLOPS
+    if kind == "mfma" and precision == "mixed-bf16":
+        w_kb = nproj / (nproj + nv)
+        return 1.0 / (w_kb * 3.0 / MI355X_BF16_TFLOPS + (1.0 - w_kb) / MI355X_FP32_TFLOPS)
+    return MI355X_FP32_TFLOPS
+
+
+def _roofline(prof, precision, nproj, nv):
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, nl, by, fl = prof[dom]
+    kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
+    if kind == "hbm":
+        roof = {"bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9, "peak": MI355X_HBM_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": kind, "achieved": fl / (ms * 1e-3) / 1e12,
+                "peak": _peak(kind, precision, nproj, nv), "unit": "TFLOP/s"}
+        if kind == "mfma" and precision == "mixed-bf16":
+            roof["peak_blend"] = {"bf16_x3_rows": int(nproj), "fp32_rows": int(nv)}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    ratio = HBM_OVER_ALGORITHMIC.get((dom, precision))
+    roof["traffic"] = None if ratio is None else ratio * by / max(nl, 1)
+    roof["traffic_unit"] = "bytes/launch"
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = ms * 1e3 / max(nl, 1)
+    roof["algorithmic_bytes_per_launch"] = by / max(nl, 1)
+    roof["algorithmic_flops_per_launch"] = fl / max(nl, 1)
+    return roof
+
+
+def run_workload(P, torch, name, npert, args, pool=None):
+    """Valence set-up, resident system, then timed steps of every requested
+    precision (profiling off, captured graphs on) and one profiled step of the
+    primary precision (per-phase kernel times, not part of the timed figures)."""
+    cfg = workloads.get_config(name)
+    nsolves = npert * cfg.nv
+    miller, vloc, beta, dij = _system(cfg)
+    ctx = P.sth_create(device=0, max_slots=args.slots)
+    try:
+        t0 = time.perf_counter()
+        eps, psi, vres, vits = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij,
+                                             cfg.nv + 1, tol=1e-10)
+        t_val = time.perf_counter() - t0
+        print(f"{name}: valence set-up {t_val:.1f} s ({vits} iterations, residual {vres:.1e})",
+              file=sys.stderr, flush=True)
+        gap = float(eps[cfg.nv] - eps[cfg.nv - 1])
+        t0 = time.perf_counter()
+        sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
+                               eps[:cfg.nv])
+        t_sys = time.perf_counter() - t0
+        if pool is not None:
+            pool.set_valence(eps[:cfg.nv], psi[:cfg.nv])
+        del psi
+        tinfo = P.sth_system_info_get(ctx, sid)
+        tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "zfft_kernel_fp64",
+                                        "fft_plan_fp32", "plane_kernel_fp32", "zfft_kernel_fp32",
+                                        "gemm_kchunk", "tuned_from_cache", "nslots")}
+        tuning["tune_ms"] = [round(x, 4) for x in tinfo["tune_ms"]]
+        bands = np.arange(cfg.nv)
+        dv = torch.from_numpy(workloads.dv_block(cfg, range(npert))).to("cuda:0")
+
+        def step(prec):
+            t = P.sth_submit_solves(ctx, sid, dv, bands, tol=args.tol, precision=prec)
+            if not P.sth_wait(ctx, t, 3600.0):
+                raise RuntimeError("step did not finish")
+            it, res, st, lat = P.sth_fetch_stats(ctx, t, nsolves)
+            P.sth_chi0_block(ctx, t, npert)
+            P.sth_release_ticket(ctx, t)
+            return it, res, st, lat
+
+        legs = {}
+        for pname in [args.precision] + ([args.compare] if args.compare and
+                                         args.compare != args.precision else []):
+            prec = PRECISIONS[pname](P)
+            for _ in range(args.warmup):
+                step(prec)
+                print(f"{name} {pname}: warm-up step done", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            mark = time.monotonic_ns()
+            t0 = time.perf_counter()
+            lats, its, bad, worst = [], [], 0, 0.0
+            for k in range(args.steps):
+                it, res, st, lat = step(prec)
+                lats.append(lat)
+                its.append(it)
+                bad += int((st != 0).sum())
+                worst = max(worst, float(res.max()))
+                print(f"{name} {pname}: step {k} done", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            print(f"{name} {pname}: timed window monotonic_ns {mark} {time.monotonic_ns()}",
+                  file=sys.stderr, flush=True)
+            lat = np.concatenate(lats) * 1e3
+            it = np.concatenate(its)
+            legs[pname] = {"value": args.steps * nsolves / dt, "ms_per_step": dt * 1e3 / args.steps,
+                           "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                          "p99": float(np.percentile(lat, 99))},
+                           "cg_iterations": {"mean": float(it.mean()), "max": int(it.max())},
+                           "not_converged": bad, "max_true_rel_residual": worst}
+        phases = roof = None
+        if not args.no_profile_step:
+            P.sth_profile(ctx, True)
+            step(PRECISIONS[args.precision](P))
+            torch.cuda.synchronize()
+            prof = P.sth_profile_read(ctx)
+            P.sth_profile(ctx, False)
+            roof = _roofline(prof, args.precision, beta.shape[0], cfg.nv)
+            phases = {k: {"ms": round(v[0], 3), "launches": v[1],
+                          "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
+                          "TFLOP/s": (round(v[3] / (v[0] * 1e-3) / 1e12, 2)
+                                      if v[0] > 0 and v[3] else None)}
+                      for k, v in prof.items()}
+            print(f"{name}: profiled step done", file=sys.stderr, flush=True)
+    finally:
+        P.sth_destroy(ctx)
+    desc = (f"{name}: {cfg.natoms}-atom synthetic crystal, {cfg.N}^3 grid, {len(miller)} plane "
+            f"waves, {cfg.nv} bands, {beta.shape[0]} KB projectors; {npert} of the workload's "
+            f"{cfg.npert} perturbations x {cfg.nv} bands = {nsolves} solves per step "
+            f"(+ Delta n and the chi0 block), tol {args.tol:g} true relative residual")
+    return {"name": name, "desc": desc, "nsolves": nsolves, "legs": legs, "roofline": roof,
+            "phases": phases, "tuning": tuning,
+            "setup": {"valence_s": t_val, "valence_iters": vits, "valence_residual": vres,
+                      "gap_Ha": gap, "set_system_s": t_sys}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cfg2")
-    ap.add_argument("--npert", type=int, default=0, help="override the perturbation count")
+    ap.add_argument("--config", default="cfg5")
+    ap.add_argument("--npert", type=int, default=0,
+                    help="perturbations per step (default: 4 for cfg5, all otherwise)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--compare", default="mixed-bf16", choices=sorted(PRECISIONS) + [""],
                     help="also time this precision on the same system (empty: skip)")
+    ap.add_argument("--extra", default="cfg2",
+                    help="second workload timed the same way after the first (empty: skip)")
     ap.add_argument("--slots", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle solves sampled (0: auto)")
+    ap.add_argument("--cpu-maxit", type=int, default=0,
+                    help="PCG iterations per sampled oracle solve (0: auto)")
+    ap.add_argument("--no-profile-step", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--valence-cache", default="",
-                    help="npz file: load the device LOBPCG states from it if present, else "
-                         "compute them on the device and save them there")
+                    help="npz file of valence states (pdep and lanczos modes)")
     ap.add_argument("--served", action="store_true",
                     help="served mode: Poisson request stream over several systems")
     ap.add_argument("--served-systems", default="cfg4a,cfg4b,cfg4c")
@@ -308,12 +529,15 @@ def main():
         lanczos_run(args)
         return
     cfg = workloads.get_config(args.config)
-    npert = args.npert or cfg.npert
-    nsolves = npert * cfg.nv
+    npert = args.npert or DEFAULT_NPERT.get(args.config, cfg.npert)
 
-    cpu = None
+    pool = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.config, args.tol, args.cpu_sample)
+        # large systems: each oracle worker holds transient copies of the
+        # projector and valence blocks (GBs), so fewer workers there
+        big = cfg.N >= 96
+        cores = min(8 if big else 16, os.cpu_count() or 1)
+        pool = OraclePool(args.config, cores)
 
     import torch
     import paper_2203_05623_amd as P
@@ -326,158 +550,50 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    miller = workloads.miller_sphere(cfg.M2)
-    vloc = workloads.vloc_r(cfg)
-    beta = workloads.beta_projectors(cfg, miller)
-    dij = workloads.dij(cfg)
-    dv = workloads.dv_block(cfg, range(npert))
-    ctx = P.sth_create(device=0, max_slots=args.slots)
-    t0 = time.perf_counter()
-    if args.valence_cache and os.path.exists(args.valence_cache):
-        # states computed by an earlier run of the device LOBPCG (profiling runs)
-        d = np.load(args.valence_cache)
-        eps, psi, vres, vits = d["eps"], d["psi"], float(d["res"]), int(d["iters"])
-    else:
-        eps, psi, vres, vits = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij,
-                                             cfg.nv + 1, tol=1e-10)
-        if args.valence_cache:
-            np.savez(args.valence_cache, eps=eps, psi=psi, res=vres, iters=vits)
-    t_val = time.perf_counter() - t0
-    gap = float(eps[cfg.nv] - eps[cfg.nv - 1])
-    sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi[:cfg.nv],
-                           eps[:cfg.nv])
-    tinfo = P.sth_system_info_get(ctx, sid)
-    tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "zfft_kernel_fp64",
-                                    "fft_plan_fp32", "plane_kernel_fp32", "zfft_kernel_fp32",
-                                    "gemm_kchunk", "tuned_from_cache")}
-    tuning["tune_ms"] = [round(x, 4) for x in tinfo["tune_ms"]]
-    prec = PRECISIONS[args.precision](P)
-    bands = np.arange(cfg.nv)
-    dv = torch.from_numpy(dv).to("cuda:0")      # inputs resident in HBM before timing
+    main_run = run_workload(P, torch, args.config, npert, args, pool)
+    cpu = None
+    if pool is not None:
+        big = cfg.N >= 96
+        nsample = args.cpu_sample or pool.cores * (1 if big else 2)
+        maxit = args.cpu_maxit or (3 if big else 1000)
+        try:
+            cpu = pool.run(npert, cfg.nv, args.tol, nsample, maxit,
+                           main_run["legs"][args.precision]["cg_iterations"]["mean"])
+        finally:
+            pool.close()
+        print("oracle baseline done", file=sys.stderr, flush=True)
+    extra = None
+    if args.extra and args.extra != args.config:
+        ecfg = workloads.get_config(args.extra)
+        extra = run_workload(P, torch, args.extra, DEFAULT_NPERT.get(args.extra, ecfg.npert),
+                             args, None)
 
-    def step():
-        t = P.sth_submit_solves(ctx, sid, dv, bands, tol=args.tol, precision=prec)
-        if not P.sth_wait(ctx, t, 3600.0):
-            raise RuntimeError("step did not finish")
-        info = P.sth_poll(ctx, t)
-        it, res, st, lat = P.sth_fetch_stats(ctx, t, nsolves)
-        _, _, lam = P.sth_chi0_block(ctx, t, npert)
-        P.sth_release_ticket(ctx, t)
-        return info, it, res, st, lat, lam
-
-    for _ in range(args.warmup):
-        step()
-        print("warmup step done", file=sys.stderr, flush=True)
-    P.sth_profile(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, lats, iters, bad, worst = [], [], [], 0, 0.0
-    for k in range(args.steps):
-        info, it, res, st, lat, lam = step()
-        infos.append(info)
-        lats.append(lat)
-        iters.append(it)
-        bad += int((st != 0).sum())
-        worst = max(worst, float(res.max()))
-        print(f"step {k} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = P.sth_profile_read(ctx)
-    P.sth_profile(ctx, False)
-    # the other precision of the metric on the same system and inputs (its own
-    # warm-up step captures its graphs), reported beside the primary figure
-    compare = None
-    if args.compare and args.compare != args.precision:
-        prec = PRECISIONS[args.compare](P)
-        for _ in range(max(args.warmup, 1)):
-            step()
-        print(f"{args.compare} warmup step done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        c_lat, c_its, c_bad, c_worst = [], [], 0, 0.0
-        for k in range(args.steps):
-            info, it, res, st, lt, _ = step()
-            c_lat.append(lt)
-            c_its.append(it)
-            c_bad += int((st != 0).sum())
-            c_worst = max(c_worst, float(res.max()))
-            print(f"{args.compare} step {k} done", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        cdt = time.perf_counter() - t1
-        cl = np.concatenate(c_lat) * 1e3
-        ci = np.concatenate(c_its)
-        compare = {"precision": args.compare, "value": args.steps * nsolves / cdt,
-                   "ms_per_step": cdt * 1e3 / args.steps,
-                   "latency_ms": {"p50": float(np.percentile(cl, 50)),
-                                  "p99": float(np.percentile(cl, 99))},
-                   "cg_iterations": {"mean": float(ci.mean()), "max": int(ci.max())},
-                   "not_converged": c_bad, "max_true_rel_residual": c_worst}
-    P.sth_destroy(ctx)
-
-    lat = np.concatenate(lats) * 1e3
-    its = np.concatenate(iters)
-    value = args.steps * nsolves / dt
-    # dominant kernel phase and its roofline: the projector GEMMs against the
-    # MFMA peak, the plane stage (FFT butterflies on the vector ALUs) against the
-    # vector ALU peak with the nominal 5 N log2 N flops per transform, the other
-    # phases against HBM bandwidth; FP64 peaks for FP64 runs, FP32 for mixed.  In
-    # the BF16-mixed form a GEMM phase holds the KB products on BF16 MFMA (each
-    # algorithmic complex-FP32 flop issued as three BF16 products: hi hi, hi lo,
-    # lo hi) and the P_c projection on FP32 MFMA; its peak is the flop-weighted
-    # harmonic blend of BF16 / 3 and FP32 over the KB and valence row counts
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, nl, by, fl = prof[dom]
-    kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
-    if kind == "hbm":
-        roof = {"bound": "hbm", "achieved": by / (ms * 1e-3) / 1e9, "peak": MI355X_HBM_GBS,
-                "unit": "GB/s"}
-    else:
-        if args.precision == "fp64":
-            peak = MI355X_FP64_TFLOPS
-        elif kind == "mfma" and args.precision == "mixed-bf16":
-            w_kb = beta.shape[0] / (beta.shape[0] + cfg.nv)
-            peak = 1.0 / (w_kb * 3.0 / MI355X_BF16_TFLOPS + (1.0 - w_kb) / MI355X_FP32_TFLOPS)
-        else:
-            peak = MI355X_FP32_TFLOPS
-        roof = {"bound": kind, "achieved": fl / (ms * 1e-3) / 1e12, "peak": peak,
-                "unit": "TFLOP/s"}
-        if kind == "mfma" and args.precision == "mixed-bf16":
-            roof["peak_blend"] = {"bf16_x3_rows": int(beta.shape[0]), "fp32_rows": int(cfg.nv)}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters (calibrated
-    # on a 1 GiB copy) as a multiple of the algorithmic bytes, where measured
-    ratio = HBM_OVER_ALGORITHMIC.get((dom, args.precision))
-    roof["traffic"] = None if ratio is None else ratio * by / max(nl, 1)
-    roof["traffic_unit"] = "bytes/launch"
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = ms * 1e3 / max(nl, 1)
-    roof["algorithmic_bytes_per_launch"] = by / max(nl, 1)
-    roof["algorithmic_flops_per_launch"] = fl / max(nl, 1)
-    phases = {k: {"ms": round(v[0], 3), "launches": v[1],
-                  "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
-                  "TFLOP/s": round(v[3] / (v[0] * 1e-3) / 1e12, 2) if v[0] > 0 and v[3] else None}
-              for k, v in prof.items()}
+    prim = main_run["legs"][args.precision]
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "metric": METRIC, "value": prim["value"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "mixed": "f32/f64", "mixed-bf16": "bf16x2/f32/f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {cfg.natoms}-atom synthetic crystal, {cfg.N}^3 grid, "
-                               f"{len(miller)} plane waves, {cfg.nv} bands, {cfg.nproj} KB "
-                               f"projectors, {npert} perturbations = {nsolves} solves/step, "
-                               f"tol {args.tol:g}, {args.precision}",
-                   "solves_per_step": nsolves, "precision": args.precision, "tol": args.tol},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "cg_iterations": {"mean": float(its.mean()), "max": int(its.max())},
-        "not_converged": bad, "max_true_rel_residual": worst,
-        "setup": {"valence_s": t_val, "valence_iters": vits, "valence_residual": vres,
-                  "gap_Ha": gap},
-        "roofline": roof, "phases": phases, "tuning": tuning, "cpu_baseline": cpu,
+        "config": {"workload": main_run["desc"] + f", {args.precision}",
+                   "solves_per_step": main_run["nsolves"], "precision": args.precision,
+                   "tol": args.tol},
+        "latency_ms": prim["latency_ms"], "cg_iterations": prim["cg_iterations"],
+        "not_converged": prim["not_converged"],
+        "max_true_rel_residual": prim["max_true_rel_residual"],
+        "setup": main_run["setup"], "roofline": main_run["roofline"],
+        "phases": main_run["phases"], "tuning": main_run["tuning"], "cpu_baseline": cpu,
     }
-    if compare is not None:
-        compare["speedup_over_" + args.precision] = compare["value"] / value
-        out["compare"] = compare
+    if args.compare and args.compare in main_run["legs"] and args.compare != args.precision:
+        c = dict(main_run["legs"][args.compare], precision=args.compare)
+        c["speedup_over_" + args.precision] = c["value"] / prim["value"]
+        out["compare"] = c
+    if extra is not None:
+        e = {"workload": extra["desc"], "solves_per_step": extra["nsolves"],
+             "setup": extra["setup"], "roofline": extra["roofline"]}
+        for k, leg in extra["legs"].items():
+            e[k] = leg
+        out["extra"] = e
     print(json.dumps(out))
 
 

@@ -85,6 +85,8 @@ typedef struct {
   size_t hbm_budget_bytes;  /* device memory the context may use; 0 = 90% of free */
   int max_slots;            /* solves in flight per system; 0 = derived from the budget */
   int check_every;          /* CG iterations between convergence polls; 0 = default (2) */
+  int max_queued;           /* requests waiting for admission (all systems) before
+                               sth_submit_solves returns STH_E_AGAIN; 0 = 1024 */
 } sth_config;
 
 typedef struct {
@@ -166,6 +168,8 @@ typedef struct {
   int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"): 0
                                                  workgroup form, 1 wave form */
   int n;                              /* FFT grid points per axis */
+  size_t budget_used, budget_limit;   /* the context's device memory in use (all systems,
+                                         slot pools, requests) and its budget, bytes */
 } sth_system_info;
 sth_status sth_system_info_get(sth_ctx* ctx, int32_t system_id, sth_system_info* info);
 
@@ -197,9 +201,16 @@ sth_status sth_valence(sth_ctx* ctx, const sth_system_desc* desc, int nbands, do
 
 /* Queues npert x nband solves: dV_j = dv_r[j] (real [npert][n^3]) for every
  * band index in bands[0..nband) (0 <= band < nv, no duplicates).  Returns at
- * once with a ticket; the server admits the request when its perturbations
- * fit the budget.  STH_E_NOMEM if it can never fit, STH_E_AGAIN if the queue
- * is full. */
+ * once with a ticket; the server admits the request when its footprint fits
+ * the budget: dV and dn of every perturbation, plus the Delta psi block
+ * [nband][npw] of every perturbation when want_dpsi is set, else of a window
+ * of perturbations in flight (enough to fill the slot pool, fewer when the
+ * budget is short, at least one).  Without want_dpsi a perturbation's block is
+ * reused once its dn is formed (in fixed band order), so a request larger than
+ * device memory (e.g. 64 perturbations x 1024 bands x 187,511 plane waves,
+ * 197 GB of Delta psi) streams through.  STH_E_NOMEM if even the smallest
+ * footprint exceeds the whole budget; STH_E_AGAIN if max_queued requests are
+ * already waiting for admission (nothing is queued; retry later). */
 sth_status sth_submit_solves(sth_ctx* ctx, int32_t system_id, int npert, const double* dv_r,
                              int nband, const int32_t* bands, const sth_solve_opts* opts,
                              int ptr_kind, void* stream, uint64_t* ticket);

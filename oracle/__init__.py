@@ -29,9 +29,9 @@ from .system import System, build_system, build_free_electron_system
 from .hamiltonian import dense_H, apply_H, kinetic, to_grid, from_grid, dense_potential_matrix
 from .valence import dense_valence, davidson_valence, lobpcg_valence
 from .response import (rhs, solve_lu, solve_sum_over_states, tpa_precond, pcg_solve,
-                       drho, chi0_block, density)
+                       drho, chi0_block, density, free_electron_response)
 
 __all__ = ["System", "build_system", "build_free_electron_system", "dense_H", "apply_H", "kinetic",
            "to_grid", "from_grid", "dense_potential_matrix", "dense_valence", "davidson_valence", "lobpcg_valence",
            "rhs", "solve_lu", "solve_sum_over_states", "tpa_precond", "pcg_solve", "drho",
-           "chi0_block", "density"]
+           "chi0_block", "density", "free_electron_response"]

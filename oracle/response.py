@@ -62,6 +62,34 @@ def solve_sum_over_states(evals: np.ndarray, evecs: np.ndarray, nv: int, v: int,
     return -(coef @ C)
 
 
+def free_electron_response(sys: System, val: np.ndarray, v: int, dv_r: np.ndarray) -> np.ndarray:
+    """Delta psi_v of a free-electron system in closed form.
+
+    For H = T + c (constant local potential c, no projectors) every plane wave
+    is an eigenvector.  With the valence set a closed shell of plane waves
+    (``val``: sphere indices of the shell, psi_v = e_{val[v]}), P_c (H - eps_v) P_c
+    is diagonal on range(P_c) with entries T(G) - T(G_v), and the right-hand
+    side -P_c (Delta V psi_v) has the entries -Delta V(G - G_v) (Fourier
+    coefficient of the forward transform with 1/N^3) outside the shell.  The
+    Sternheimer equation (Section 3) then has the solution
+        Delta psi_v(G) = -Delta V(G - G_v) / (T(G) - T(G_v)),  G outside the shell,
+    and 0 inside it.  The shell must be closed: every G outside it has
+    T(G) > T(G_v)."""
+    m = sys.miller.astype(np.int64)
+    T = kinetic(sys)
+    inside = np.zeros(sys.npw, bool)
+    inside[val] = True
+    gv = val[v]
+    if not (T[~inside].min() > T[val].max()):
+        raise ValueError("free_electron_response: the valence set is not a closed shell")
+    dVG = np.fft.fftn(dv_r.reshape((sys.N,) * 3)) / sys.N ** 3
+    d = np.mod(m - m[gv], sys.N)
+    x = np.zeros(sys.npw, complex)
+    out = ~inside
+    x[out] = -dVG[d[out, 0], d[out, 1], d[out, 2]] / (T[out] - T[gv])
+    return x
+
+
 # ---------------------------------------------------------------- PCG
 EKIN_FLOOR = 0.1   # Ha; keeps x finite for a band with (almost) no kinetic energy
 

@@ -32,7 +32,7 @@ PHASES = ["zfft_inv", "plane", "zfft_fwd", "gemm_ah_b", "reduce", "gemm_a_c", "c
 
 class sth_config(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("max_queued", C.c_int)]
 
 
 class sth_system_desc(C.Structure):
@@ -62,7 +62,8 @@ class sth_system_info(C.Structure):
                 ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 32),
                 ("tuned_from_cache", C.c_int), ("plane_kernel_fp64", C.c_int),
                 ("plane_kernel_fp32", C.c_int), ("zfft_kernel_fp64", C.c_int),
-                ("zfft_kernel_fp32", C.c_int), ("n", C.c_int)]
+                ("zfft_kernel_fp32", C.c_int), ("n", C.c_int), ("budget_used", C.c_size_t),
+                ("budget_limit", C.c_size_t)]
 
 
 class SthError(RuntimeError):
@@ -183,8 +184,8 @@ def _stream(a=None):
 
 
 # ------------------------------------------------------------------ C-ABI functions
-def sth_create(device=0, hbm_budget_bytes=0, max_slots=0, check_every=0):
-    cfg = sth_config(device, hbm_budget_bytes, max_slots, check_every)
+def sth_create(device=0, hbm_budget_bytes=0, max_slots=0, check_every=0, max_queued=0):
+    cfg = sth_config(device, hbm_budget_bytes, max_slots, check_every, max_queued)
     h = C.c_void_p()
     _check(lib().sth_create(C.byref(cfg), C.byref(h)))
     return h

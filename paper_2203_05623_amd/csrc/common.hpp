@@ -37,6 +37,22 @@ __host__ __device__ inline cpx<T> mul_i(cpx<T> a) {
   return SIGN < 0 ? cpx<T>{a.y, -a.x} : cpx<T>{-a.y, a.x};
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin by linear id, and
+// each XCD has its own L2.  The logical tile (x, y, z) of a workgroup is taken
+// so that every XCD gets one contiguous range of logical ids in x-fastest
+// order: tiles that share an operand along x run on one XCD, one after the
+// other.  A bijection of the grid for any size.
+__device__ inline void xcd_tile3(int& x, int& y, int& z) {
+  const long long gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const long long T = gx * gy * gz;
+  const long long L = blockIdx.x + gx * (blockIdx.y + gy * (long long)blockIdx.z);
+  const long long q = T / 8, r = T % 8, xcd = L % 8, j = L / 8;
+  const long long lg = xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+  x = int(lg % gx);
+  y = int((lg / gx) % gy);
+  z = int(lg / (gx * gy));
+}
+
 }  // namespace sth
 
 #define STH_HIP_CHECK(expr)                                                      \

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -120,7 +121,8 @@ void check_ptr_kind(int k) {
 // ------------------------------------------------------------------ context
 Context::Context(const sth_config& cfg)
     : device_(cfg.device), budget_(0), max_slots_(cfg.max_slots),
-      check_every_(cfg.check_every > 0 ? cfg.check_every : 2) {
+      check_every_(cfg.check_every > 0 ? cfg.check_every : 2),
+      max_queued_(cfg.max_queued > 0 ? cfg.max_queued : 1024) {
   int ndev = 0;
   STH_HIP_CHECK(hipGetDeviceCount(&ndev));
   if (cfg.device < 0 || cfg.device >= ndev) {
@@ -432,6 +434,7 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   std::lock_guard<std::mutex> glk(gpu_mu_);
   STH_HIP_CHECK(hipSetDevice(device_));
   order_after(user);
+  const size_t used0 = budget_.used();   // every allocation is made under gpu_mu_
   auto sp = std::make_unique<System>();
   System& s = *sp;
   // host copies of the small per-band inputs
@@ -529,6 +532,7 @@ int Context::set_system(const sth_system_desc& d, hipStream_t user) {
   s.d_drho_sticks = DevMem(&budget_, (size_t)s.nv * N * s.nst * sizeof(z64));
   STH_HIP_CHECK(hipStreamSynchronize(st_));
 
+  s.resident_bytes = budget_.used() - used0;
   std::lock_guard<std::mutex> lk(mu_);
   s.id = next_sys_++;
   const int id = s.id;
@@ -552,6 +556,7 @@ void Context::release_system(int id) {
     }
   (void)hipStreamSynchronize(st_);
   systems_.erase(it);
+  ++mem_epoch_;
   cv_.notify_all();
 }
 
@@ -850,6 +855,18 @@ uint64_t Context::submit(int id, int npert, const double* dv, int nband, const i
               "STH_MIXED_BF16 required");
     throw Error(STH_E_INVALID);
   }
+  auto queued = [&]() {   // requests waiting for admission, all systems (mu_ held)
+    size_t q = 0;
+    for (auto& kv : systems_) q += kv.second->waiting.size();
+    return q;
+  };
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (queued() >= size_t(max_queued_)) {
+      set_error("submit: %d requests are already waiting for admission", max_queued_);
+      throw Error(STH_E_AGAIN);
+    }
+  }
   std::lock_guard<std::mutex> glk(gpu_mu_);
   STH_HIP_CHECK(hipSetDevice(device_));
   System& s = sys(id);
@@ -861,10 +878,17 @@ uint64_t Context::submit(int id, int npert, const double* dv, int nband, const i
     }
   }
   const long long n3 = (long long)s.N * s.N * s.N;
-  const size_t need = (size_t)npert * n3 * 8 * 2 + (size_t)npert * nband * s.npw * 16;
-  if (need > budget_.limit() - std::min(budget_.limit(), budget_.used()) + 0 &&
-      need > budget_.limit()) {
-    set_error("request needs %zu bytes, more than the whole budget %zu", need, budget_.limit());
+  // smallest footprint the request can run in: dV and Delta n, and the Delta psi
+  // of every perturbation (want_dpsi) or of one perturbation at a time; it must
+  // fit the budget left by the resident systems (requests and tickets come and go)
+  const size_t need = (size_t)npert * n3 * 8 * 2 +
+                      (size_t)(o.want_dpsi ? npert : 1) * nband * s.npw * 16 + nband * 4;
+  size_t resident = 0;
+  for (auto& kv : systems_) resident += kv.second->resident_bytes;
+  const size_t room = budget_.limit() - std::min(budget_.limit(), resident);
+  if (need > room) {
+    set_error("request needs %zu bytes, more than the %zu the budget leaves next to the "
+              "resident systems", need, room);
     throw Error(STH_E_NOMEM);
   }
   auto r = std::make_shared<Request>();
@@ -889,9 +913,14 @@ uint64_t Context::submit(int id, int npert, const double* dv, int nband, const i
   r->pert_left.assign(npert, nband);
   r->t_submit = now_s();
   std::lock_guard<std::mutex> lk(mu_);
+  if (queued() >= size_t(max_queued_)) {   // filled by another thread meanwhile
+    set_error("submit: %d requests are already waiting for admission", max_queued_);
+    throw Error(STH_E_AGAIN);
+  }
   r->ticket = next_ticket_++;
   tickets_[r->ticket] = r;
   s.waiting.push_back(r);
+  ++mem_epoch_;
   cv_.notify_all();
   return r->ticket;
 }
@@ -977,6 +1006,11 @@ void Context::fetch_dpsi(uint64_t t, double* out, int ptr_kind, hipStream_t user
   STH_HIP_CHECK(hipSetDevice(device_));
   System& s = sys(r->sys_id);
   order_after(user);
+  for (int j = 0; j < r->npert; ++j)
+    if (r->blk_of[j] != j) {   // want_dpsi requests keep block j for perturbation j
+      set_error("fetch_dpsi: Delta psi block of perturbation %d missing", j);
+      throw Error(STH_E_INTERNAL);
+    }
   const int nv = r->npert * r->nband;
   const int chunk = std::min(nv, 1024);
   DevMem tmp(&budget_, (size_t)chunk * s.npw * sizeof(z64));
@@ -1024,6 +1058,8 @@ void Context::release_ticket(uint64_t t) {
     }
   }
   tickets_.erase(it);
+  ++mem_epoch_;
+  cv_.notify_all();
 }
 
 // ------------------------------------------------------------------ server
@@ -1033,16 +1069,20 @@ void Context::server_loop() {
     std::vector<System*> work;
     {
       std::unique_lock<std::mutex> lk(mu_);
+      // a system has work when it runs requests, or holds waiting ones and memory
+      // may have been freed since admission last found no room
+      auto busy = [&](const System& sy) {
+        return !sy.running.empty() || (!sy.waiting.empty() && sy.blocked_epoch != mem_epoch_);
+      };
       cv_.wait(lk, [&] {
         if (stop_) return true;
         for (auto& kv : systems_)
-          if (!kv.second->waiting.empty() || !kv.second->running.empty()) return true;
+          if (busy(*kv.second)) return true;
         return false;
       });
       if (stop_) return;
       for (auto& kv : systems_)
-        if (!kv.second->waiting.empty() || !kv.second->running.empty())
-          work.push_back(kv.second.get());
+        if (busy(*kv.second)) work.push_back(kv.second.get());
     }
     for (System* sp : work) {
       std::lock_guard<std::mutex> glk(gpu_mu_);
@@ -1074,20 +1114,29 @@ void Context::admit(System& s) {
   while (!s.waiting.empty()) {
     auto r = s.waiting.front();
     const long long n3 = (long long)s.N * s.N * s.N;
-    const size_t need = (size_t)r->npert * r->nband * s.npw * sizeof(z64) +
-                        (size_t)r->npert * n3 * sizeof(double) + r->nband * sizeof(int);
+    const size_t blk = (size_t)r->nband * s.npw * sizeof(z64);
+    const size_t fixed = (size_t)r->npert * n3 * sizeof(double) + r->nband * sizeof(int);
+    // Delta psi window: every perturbation when the caller fetches Delta psi;
+    // otherwise enough perturbations to fill every slot plus one whose Delta n
+    // is being formed, fewer if the budget is short (down to one)
+    const int lo = r->want_dpsi ? r->npert : 1;
+    int win = r->want_dpsi ? r->npert
+                           : std::min(r->npert, (s.nslots + r->nband - 1) / r->nband + 1);
+    while (win > lo && !budget_.fits(fixed + win * blk)) --win;
+    const size_t need = fixed + win * blk;
     if (!budget_.fits(need)) {
-      if (s.running.empty()) {   // nothing will ever free memory for it
-        r->failed = true;
-        r->fail_code = STH_E_NOMEM;
-        r->state = 3;
-        s.waiting.pop_front();
-        cv_.notify_all();
-        continue;
-      }
+      // it fits once requests finish and their tickets are released (submit
+      // checked the room next to the resident systems); until then it waits,
+      // and with nothing of this system running the server sleeps until memory
+      // may have been freed
+      if (s.running.empty()) s.blocked_epoch = mem_epoch_;
       break;
     }
-    r->d_dpsi = DevMem(&budget_, (size_t)r->npert * r->nband * s.npw * sizeof(z64));
+    r->d_dpsi = DevMem(&budget_, win * blk);
+    r->win = win;
+    r->blk_of.assign(r->npert, -1);
+    r->free_blk.clear();
+    for (int b = 0; b < win; ++b) r->free_blk.push_back(b);
     r->d_drho = DevMem(&budget_, (size_t)r->npert * n3 * sizeof(double));
     r->d_bands = DevMem(&budget_, (size_t)r->nband * sizeof(int));
     STH_HIP_CHECK(hipMemcpyAsync(r->d_bands.as<void>(), r->bands.data(), r->nband * sizeof(int),
@@ -1115,6 +1164,13 @@ void Context::refill(System& s) {
     while (r->next < total) {
       while (slot < s.nslots && s.slots[slot].req) ++slot;
       if (slot >= s.nslots) break;
+      // a perturbation starts only with a Delta psi block of its own
+      const int jn = r->next / r->nband;
+      if (r->blk_of[jn] < 0) {
+        if (r->free_blk.empty()) break;
+        r->blk_of[jn] = r->free_blk.front();
+        r->free_blk.pop_front();
+      }
       const int solve = r->next++;
       const int j = solve / r->nband, vi = solve % r->nband, v = r->bands[vi];
       s.slots[slot] = SlotHost{r.get(), solve, t, 0};
@@ -1296,9 +1352,11 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
                   {nullptr, 0}, nullptr, st_);
   std::map<Request*, std::pair<std::vector<int>, std::vector<int>>> by_req;
   for (int slot : fin) {
-    auto& e = by_req[s.slots[slot].req];
+    Request* r = s.slots[slot].req;
+    const int solve = s.slots[slot].solve;
+    auto& e = by_req[r];
     e.first.push_back(slot);
-    e.second.push_back(s.slots[slot].solve);
+    e.second.push_back(r->blk_of[solve / r->nband] * r->nband + solve % r->nband);
   }
   for (auto& kv : by_req) {
     int* ds = upload_list(s, kv.second.first);
@@ -1314,6 +1372,11 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
     Request* r = sh.req;
     const int st = h_status[slot];
     const double rel = h_bn2[slot] > 0 ? std::sqrt(h_rn2[slot] / h_bn2[slot]) : 0.0;
+    if (st == SLOT_DONE && rel > 1.001 * r->tol)   // cannot happen: the check bounds it
+      std::fprintf(stderr, "sth: internal: slot %d retired converged with residual %.3e > tol "
+                   "%.1e (iterations %d, ||r||^2 %.3e, ||b||^2 %.3e, ticket %llu, solve %d)\n",
+                   slot, rel, r->tol, h_iters[slot], h_rn2[slot], h_bn2[slot],
+                   (unsigned long long)r->ticket, sh.solve);
     r->iters[sh.solve] = h_iters[slot];
     r->resid[sh.solve] = rel;
     r->status[sh.solve] = st == SLOT_DONE        ? STH_SOLVE_CONVERGED
@@ -1351,7 +1414,8 @@ void Context::finish_drho(System& s) {
       int* dl = upload_list(s, id);
       VecSet<z64> sticks{s.d_drho_sticks.as<z64>(), (long long)s.N * s.nst};
       launch_zfft_inv<double, z64>(
-          s.g, {r->d_dpsi.as<const z64>() + (size_t)j * r->nband * s.npw, (long long)s.npw},
+          s.g,
+          {r->d_dpsi.as<const z64>() + (size_t)r->blk_of[j] * r->nband * s.npw, (long long)s.npw},
           sticks, dl, r->nband, st_);
       launch_drho(s.g, s.d_drho_sticks.as<z64>(), (long long)s.N * s.nst, r->nband,
                   r->d_bands.as<int>(), s.d_psir.as<z64>(), 1, 2.0 * s.fs / s.omega,
@@ -1360,6 +1424,10 @@ void Context::finish_drho(System& s) {
       s.lists_used -= r->nband;
       std::lock_guard<std::mutex> lk(mu_);
       r->n_drho_done += 1;
+      if (!r->want_dpsi) {   // the block serves the next perturbation
+        r->free_blk.push_back(r->blk_of[j]);
+        r->blk_of[j] = -1;
+      }
     }
     std::lock_guard<std::mutex> lk(mu_);
     if (r->n_finished == r->npert * r->nband && r->n_drho_done == r->npert) {

@@ -177,6 +177,10 @@ struct System {
       if (gx) (void)hipGraphExecDestroy(gx);
   }
 
+  size_t resident_bytes = 0;       // device memory of the system and its slot pool
+  // value of the context's memory epoch when admission last found no room with
+  // nothing of this system running (the server then waits for memory to be freed)
+  unsigned long long blocked_epoch = ~0ull;
   std::deque<std::shared_ptr<Request>> waiting;   // submitted, not admitted
   std::vector<std::shared_ptr<Request>> running;  // admitted, unfinished
 
@@ -196,7 +200,15 @@ struct Request {
   int maxit = 1000, precision = 0, want_dpsi = 0;
   std::vector<double> dv_host;       // until admission
   DevMem d_dv;                       // [npert][N^3]
-  DevMem d_dpsi;                     // [npert][nband][npw] internal order
+  // Delta psi blocks: `win` blocks of [nband][npw] (internal order), one per
+  // perturbation in flight.  A request submitted with want_dpsi holds one block
+  // per perturbation (block j = perturbation j, kept for fetch_dpsi); otherwise a
+  // block returns to the free list once its perturbation's Delta n is formed, so
+  // a request of any size streams through a bounded window.
+  DevMem d_dpsi;                     // [win][nband][npw]
+  int win = 0;
+  std::vector<int> blk_of;           // per perturbation: its block, -1 when none
+  std::deque<int> free_blk;          // unassigned blocks, handed out in order
   DevMem d_drho;                     // [npert][N^3]
   DevMem d_bands;                    // [nband]
   // progress (guarded by the context mutex)
@@ -292,7 +304,7 @@ class Context {
 
   int device_;
   Budget budget_;
-  int max_slots_, check_every_;
+  int max_slots_, check_every_, max_queued_;
   bool use_graphs_ = true;
   hipStream_t st_ = nullptr;
   std::mutex mu_;        // tickets, systems map, request progress
@@ -303,6 +315,9 @@ class Context {
   std::map<int, std::unique_ptr<System>> systems_;
   std::map<uint64_t, std::shared_ptr<Request>> tickets_;
   int next_sys_ = 1;
+  // bumped (under mu_) whenever device memory may have been freed or a request
+  // queued: ticket and system releases, submissions
+  unsigned long long mem_epoch_ = 0;
   uint64_t next_ticket_ = 1;
 
   struct ProfRec {

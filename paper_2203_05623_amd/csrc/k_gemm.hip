@@ -65,7 +65,9 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
   __shared__ cpx<T> Bs[GT][GK + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT, s = blockIdx.z;
+  int tx, ty, s;
+  xcd_tile3(tx, ty, s);   // the m-tiles sharing a block of vectors run on one XCD
+  const int m0 = tx * GT, n0 = ty * GT;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
   V4 accr[2][2], acci[2][2];
 #pragma unroll

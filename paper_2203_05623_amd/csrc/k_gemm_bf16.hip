@@ -75,7 +75,9 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
   __shared__ bz Bs[2][BT][BKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int m0 = blockIdx.x * BT, n0 = blockIdx.y * BT, s = blockIdx.z;
+  int tx, ty, s;
+  xcd_tile3(tx, ty, s);   // the m-tiles sharing a block of vectors run on one XCD
+  const int m0 = tx * BT, n0 = ty * BT;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
   const int kq = lane >> 4, r16 = lane & 15;
   f4 accr[2][2], acci[2][2];

@@ -210,6 +210,8 @@ void Context::system_info(int id, sth_system_info* info) {
   for (int i = 0; i < 32; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
   info->n = s.N;
+  info->budget_used = budget_.used();
+  info->budget_limit = budget_.limit();
 }
 
 }  // namespace sth

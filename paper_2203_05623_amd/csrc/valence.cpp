@@ -304,6 +304,17 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
       L.copy(X, L.tmp1.as<z64>(), nb);
       L.copy(HX, L.tmp2.as<z64>(), nb);
     };
+    // per-phase wall time of an iteration (progress lines only: the stream is
+    // drained before each reading)
+    auto t_lap = std::chrono::steady_clock::now();
+    auto lap = [&]() {
+      if (!verbose) return 0.0;
+      STH_HIP_CHECK(hipStreamSynchronize(st_));
+      const auto t = std::chrono::steady_clock::now();
+      const double d = std::chrono::duration<double>(t - t_lap).count();
+      t_lap = t;
+      return d;
+    };
     rr_rotate();
     double a0 = th[0];
     for (; it < maxit; ++it) {
@@ -327,6 +338,7 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
         set_error("valence: empty filter interval (upper bound %.6f, theta_nb %.6f)", bup, a);
         throw Error(STH_E_INTERNAL);
       }
+      lap();
       double sigma = e / (a0 - c);
       const double tau = 2.0 / sigma;
       z64* xp = X;          // previous filtered block
@@ -344,13 +356,20 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
         yn = t;
         sigma = sn;
       }
+      const double t_f = lap();
       if (L.orth(yc, nb, nullptr, nullptr, 0, nullptr) != nb) {
         set_error("valence: filtered block lost rank");
         throw Error(STH_E_INTERNAL);
       }
+      const double t_o = lap();
       X = yc;
       h_block(s, hw, X, HX, nb);
+      const double t_h = lap();
       rr_rotate();
+      const double t_r = lap();
+      if (verbose)
+        std::fprintf(stderr, "valence: filter %.2f s, orthonormalisation %.2f s, H %.2f s, "
+                             "Rayleigh-Ritz %.2f s\n", t_f, t_o, t_h, t_r);
       a0 = std::min(a0, th[0]);
     }
   }

@@ -1,15 +1,15 @@
-"""Computes oracle valence states of a workload and caches them (oracle only).
+"""Computes oracle valence states of a workload and stores them (oracle only).
 
-The full-size GPU parity tests compare Delta psi against the oracle's PCG for
-sampled (perturbation, band) pairs; both sides must use the same psi_v, and
-the oracle's block LOBPCG takes minutes at these sizes, so its result is
-cached under tests/_cache/ (not committed; regenerate with this script).
+The full-size GPU parity tests compare against the oracle on systems whose
+valence states take the oracle's block LOBPCG minutes to an hour; both sides
+must use the same psi_v, so the oracle's result is stored under
+tests/oracle_data/ (compressed npz, committed) and read by the tests.
 
     python tests/golden/make_valence_cache.py cfg2 [tol] [nv]
 
-A band count `nv` below the workload's keeps only the lowest nv valence bands
-(cache file ..._nv{nv}_valence.npz): the parity tests of the 144^3 grid solve
-for the lowest band only, which keeps the oracle's eigensolve short.
+The file holds the lowest nv + 1 eigenpairs (the extra one gives the gap) of
+the nv + 8 the LOBPCG iterates.  A band count `nv` below the workload's keeps
+only the lowest nv valence bands (file ..._nv{nv}_valence.npz).
 """
 import os
 import sys
@@ -23,13 +23,13 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import workloads  # noqa: E402
 
-CACHE = os.path.join(ROOT, "tests", "_cache")
+DATA = os.path.join(ROOT, "tests", "oracle_data")
 
 
 def cache_path(name: str, nv: int = 0) -> str:
     cfg = workloads.get_config(name)
     tag = f"_nv{nv}" if nv and nv != cfg.nv else ""
-    return os.path.join(CACHE, f"{name}_seed{cfg.seed_kb}{tag}_valence.npz")
+    return os.path.join(DATA, f"{name}_seed{cfg.seed_kb}{tag}_valence.npz")
 
 
 def main():
@@ -43,8 +43,10 @@ def main():
     t0 = time.time()
     nb = cfg.nv + 8
     eps, psi, res, it = oracle.lobpcg_valence(s, nb, tol=tol, nconv=cfg.nv + 1, verbose=True)
-    os.makedirs(CACHE, exist_ok=True)
-    np.savez(cache_path(name, nv), eps=eps, psi=psi, res=res, iters=it, tol=tol)
+    os.makedirs(DATA, exist_ok=True)
+    keep = cfg.nv + 1
+    np.savez_compressed(cache_path(name, nv), eps=eps[:keep], psi=psi[:keep], res=res, iters=it,
+                        tol=tol)
     print(f"{name}: {nb} bands, residual {res:.2e}, {it} iterations, {time.time() - t0:.0f} s, "
           f"gap {eps[cfg.nv] - eps[cfg.nv - 1]:.6f} Ha -> {cache_path(name, nv)}")
 

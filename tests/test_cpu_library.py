@@ -67,7 +67,7 @@ def test_struct_layouts_match_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     assert got == want
-    assert C.sizeof(_lib.sth_config) == 24
+    assert C.sizeof(_lib.sth_config) == 32
     assert _lib.sth_system_desc.ptr_kind.offset == 88
 
 

@@ -1,33 +1,33 @@
-"""GPU parity at the benchmark's full size (64-atom crystal, 72^3 grid, 22,575 plane
-waves, 128 bands, 256 KB projectors), in the launch configuration bench.py uses
-(2048 slots), on sampled outputs the oracle computes one by one.
+"""GPU parity at the 64-atom crystal's full size (72^3 grid, 22,575 plane waves,
+128 bands, 256 KB projectors), in a 2048-slot context (full-width launches).
 
-The oracle's valence states come from tests/_cache (written by
-tests/golden/make_valence_cache.py, oracle only); both sides use them.
+The oracle's valence states and its PCG responses of perturbations 0 and 1
+over all 128 bands (Delta n, the chi0 block, four sampled Delta psi) are
+stored in tests/oracle_data/ by tests/golden/make_valence_cache.py and
+make_response_cache.py (oracle only); both sides use the same valence states.
 """
-import os
-
 import numpy as np
 import pytest
 
 import oracle
+import oracle_store
 import workloads
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
 CFG = workloads.get_config("cfg2")
-CACHE = os.path.join(ROOT, "tests", "_cache", f"cfg2_seed{CFG.seed_kb}_valence.npz")
-SAMPLES = [(0, 0), (0, 127), (1, 64), (1, 100)]
 
 
 @pytest.fixture(scope="module")
 def ref():
-    if not os.path.exists(CACHE):
-        pytest.skip(f"oracle valence cache missing: run tests/golden/make_valence_cache.py cfg2")
-    d = np.load(CACHE)
+    eps, psi = oracle_store.valence("cfg2")
     s = oracle.build_system("cfg2")
-    return s, d["eps"], d["psi"]
+    return s, eps, psi
+
+
+@pytest.fixture(scope="module")
+def resp():
+    return oracle_store.load("cfg2", "response")
 
 
 @pytest.fixture(scope="module")
@@ -63,24 +63,15 @@ def test_valence_matches_oracle(sth, ref, alg, monkeypatch):
     assert err < 1e-10
 
 
-def _oracle_dpsi(s, eps, psi, j, v, tol):
-    nv = CFG.nv
-    Psi, e = psi[:nv], eps[:nv]
-    b = oracle.rhs(s, Psi, v, workloads.dv_r(CFG, j))
-    x, it, rel, st = oracle.pcg_solve(s, Psi, e, v, b, tol=tol)
-    assert st == 0
-    return x
-
-
 @pytest.fixture(scope="module")
-def oracle_samples(ref):
-    s, eps, psi = ref
-    return {jv: _oracle_dpsi(s, eps, psi, *jv, tol=1e-12) for jv in SAMPLES}
+def oracle_samples(resp):
+    return {(int(j), int(v)): x for (j, v), x in zip(resp["samples"], resp["dpsi_samples"])}
 
 
 @pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6),
                                                  ("mixed-bf16", 1e-8, 1e-6)])
-def test_sampled_solves_match_oracle(sth, ref, sys2, oracle_samples, precision, tol, bound):
+def test_sampled_solves_match_oracle(sth, ref, resp, sys2, oracle_samples, precision, tol,
+                                    bound):
     P, ctx = sth
     s, eps, psi = ref
     npert = 2
@@ -103,4 +94,15 @@ def test_sampled_solves_match_oracle(sth, ref, sys2, oracle_samples, precision, 
     # every solution is orthogonal to the valence manifold
     ov = np.abs(np.einsum("vg,jwg->jwv", psi[:CFG.nv].conj(), dpsi)).max()
     assert ov < 1e-10 * np.abs(dpsi).max() * np.sqrt(s.npw)
+    # Delta n of both perturbations over all 128 bands and the chi0 block
+    dn = np.empty((npert, CFG.N, CFG.N, CFG.N))
+    P.sth_fetch_drho(ctx, t, dn)
+    M, S, lam = P.sth_chi0_block(ctx, t, npert)
     P.sth_release_ticket(ctx, t)
+    ref_dn = resp["drho"]
+    e_dn = np.abs(dn - ref_dn).max() / np.abs(ref_dn).max()
+    e_m = np.abs(M - resp["M"]).max() / np.abs(resp["M"]).max()
+    e_l = np.abs(lam - resp["lam"]).max() / np.abs(resp["lam"]).max()
+    print(precision, f"dn {e_dn:.2e}, M {e_m:.2e}, chi0 eigenvalues {e_l:.2e}")
+    assert e_dn < bound and e_m < bound and e_l < bound
+    assert np.allclose(S, resp["S"], rtol=1e-13, atol=0)

@@ -5,7 +5,7 @@ PDEP vectors), through the C-ABI, against oracle/lanczos.py on the same inputs:
 alpha, beta and the tridiagonal eigenvalues within 1e-10 relative, the braket
 <u_n|q^l_m> within 1e-10 of its largest entry, and the tridiagonal eigenvectors
 up to the sign of each.  Config 1 (30 steps, 3 chains) and the benchmark system
-(20 steps, 2 chains; oracle valence states from tests/_cache).
+(20 steps, 2 chains; oracle valence states from tests/oracle_data).
 """
 import os
 
@@ -14,6 +14,7 @@ import pytest
 import scipy.fft
 
 import oracle
+import oracle_store
 import workloads
 from oracle import lanczos, pdep
 
@@ -65,12 +66,9 @@ def test_lanczos_cfg1(cfg1_system, cfg1_dense):
 def test_lanczos_cfg2():
     import paper_2203_05623_amd as P
     cfg = workloads.get_config("cfg2")
-    cache = os.path.join(ROOT, "tests", "_cache", f"cfg2_seed{cfg.seed_kb}_valence.npz")
-    if not os.path.exists(cache):
-        pytest.skip("oracle valence cache missing: run tests/golden/make_valence_cache.py cfg2")
-    d = np.load(cache)
+    eps, psi = oracle_store.valence("cfg2")
     s = oracle.build_system("cfg2")
-    psi, eps = d["psi"][:cfg.nv], d["eps"][:cfg.nv]
+    psi, eps = psi[:cfg.nv], eps[:cfg.nv]
     phi = np.stack([_band_limited_real(s, 30 + k) for k in range(2)])
     ref = lanczos.lanczos_block(s, psi[127], phi, 20)
     ctx = P.sth_create(device=0, max_slots=64)

@@ -8,26 +8,25 @@ kernels runs there.  Calls go through the C-ABI.
 * H.psi against the oracle's FFT route, 1e-12 relative, on both grids.
 * 144^3: Sternheimer solves for the lowest band and two perturbations, FP64 at
   tolerance 1e-12 (Delta psi and Delta n within 1e-10) and STH_MIXED_BF16 at
-  1e-8 (Delta psi within 1e-6), against the oracle's PCG solutions cached by
-  tests/golden/make_response_cache.py from the oracle valence states of
-  tests/golden/make_valence_cache.py (skipped when the caches are missing).
-  The oracle's LOBPCG is run to residual 3e-9 at this size (it stalls near
-  2e-9); both sides take the same psi_0 and solve the same projected
-  equation, so that residual enters both alike.
+  1e-8 (Delta psi within 1e-6), against the oracle's PCG solutions stored in
+  tests/oracle_data/ by tests/golden/make_response_cache.py from the oracle
+  valence state of tests/golden/make_valence_cache.py; the oracle forms Delta n
+  of that band from them.  The oracle's LOBPCG is run to residual 3e-9 at this
+  size (it stalls near 2e-9); both sides take the same psi_0 and solve the
+  same projected equation, so that residual enters both alike.  (Every band of
+  a many-band valence set at 96^3 and 144^3 is checked on free-electron closed
+  shells in test_gpu_closed_shell.py.)
 """
 import functools
-import os
 
 import numpy as np
 import pytest
 
 import oracle
+import oracle_store
 import workloads
 
 pytestmark = pytest.mark.gpu
-
-ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
-CACHE = os.path.join(ROOT, "tests", "_cache")
 
 
 @pytest.fixture(scope="module")
@@ -77,15 +76,12 @@ def test_apply_h_large_grid(sth, name):
 def test_solves_144_lowest_band(sth):
     P, ctx = sth
     cfg = workloads.get_config("cfg5")
-    vpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_valence.npz")
-    rpath = os.path.join(CACHE, f"cfg5_seed{cfg.seed_kb}_nv1_response.npz")
-    if not (os.path.exists(vpath) and os.path.exists(rpath)):
-        pytest.skip("oracle caches missing: run tests/golden/make_valence_cache.py cfg5 3e-9 1 "
-                    "and tests/golden/make_response_cache.py cfg5 1")
-    d, r = np.load(vpath), np.load(rpath)
+    eps, psi = oracle_store.valence("cfg5", nv=1)
+    r = oracle_store.load("cfg5", "response", nv=1)
     s = _system("cfg5")
-    psi, eps = np.ascontiguousarray(d["psi"][:1]), d["eps"][:1]
-    ref_x, ref_dn = r["dpsi"], r["drho"]
+    psi, eps = np.ascontiguousarray(psi[:1]), eps[:1]
+    ref_x = r["dpsi"]
+    ref_dn = np.stack([oracle.drho(s, psi, ref_x[j][None]) for j in range(ref_x.shape[0])])
     npert = ref_x.shape[0]
     dv = workloads.dv_block(cfg, range(npert))
     sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)

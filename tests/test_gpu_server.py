@@ -1,0 +1,275 @@
+"""GPU tests of the solve server through the C-ABI: admission by device-memory
+footprint, the Delta psi window, queueing, failure isolation and determinism.
+
+The equations are independent per perturbation and band (paper, Section 3), so
+the server may place any solve in any slot next to any other solve; these tests
+check that this freedom changes no result:
+
+* a request without want_dpsi streams its perturbations through a window of
+  Delta psi blocks (fewer than its perturbations), and its Delta n equals,
+  bit for bit, that of the same request holding every block, and the oracle's;
+* under a budget that fits only part of a request's window, it is admitted in
+  waves of perturbations with the same Delta n; a request that can never fit is
+  refused with STH_E_NOMEM; a full admission queue answers STH_E_AGAIN and an
+  early fetch STH_E_NOT_READY;
+* a perturbation with a non-finite value fails its own solves (STH_SOLVE_NAN)
+  and leaves the other perturbations' results unchanged;
+* results of a request served next to other requests, on other systems of
+  other grid sizes in the same context, equal bit for bit those of the request
+  served alone.
+
+System: the 8-atom crystal (24^3 grid, 587 plane waves, 8 bands from dense
+diagonalisation), and for the second grid the 27-atom simple-cubic cell on a
+48^3 grid (6,403 plane waves, 54 bands from the oracle's LOBPCG stored in
+tests/oracle_data/).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+CFG = workloads.get_config("cfg1")
+NV = CFG.nv
+
+
+@pytest.fixture(scope="module")
+def cfg1(cfg1_system, cfg1_dense):
+    H, w, V = cfg1_dense
+    return cfg1_system, H, w[:NV], np.ascontiguousarray(V[:NV])
+
+
+def _set(P, ctx, s, Psi, eps, cfg=CFG):
+    return P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, Psi, eps)
+
+
+def _run(P, ctx, sid, dv, nband, tol=1e-12, want_dpsi=False, timeout=120.0, precision=0):
+    t = P.sth_submit_solves(ctx, sid, dv, np.arange(nband), tol=tol, want_dpsi=want_dpsi,
+                            precision=precision)
+    assert P.sth_wait(ctx, t, timeout)
+    n = P.sth_system_info_get(ctx, sid)["n"]
+    dn = np.empty((len(dv), n, n, n))
+    P.sth_fetch_drho(ctx, t, dn)
+    it, res, st, _ = P.sth_fetch_stats(ctx, t, len(dv) * nband)
+    dpsi = None
+    if want_dpsi:
+        npw = P.sth_system_info_get(ctx, sid)["npw"]
+        dpsi = np.empty((len(dv), nband, npw), np.complex128)
+        P.sth_fetch_dpsi(ctx, t, dpsi)
+    P.sth_release_ticket(ctx, t)
+    return dn, dpsi, st.reshape(len(dv), nband), res.reshape(len(dv), nband)
+
+
+def _oracle_dn(s, H, Psi, eps, dv):
+    out = []
+    for j in range(len(dv)):
+        x = np.stack([oracle.solve_lu(H, Psi, eps[v], oracle.rhs(s, Psi, v, dv[j]))
+                      for v in range(NV)])
+        out.append(oracle.drho(s, Psi, x))
+    return np.stack(out)
+
+
+def test_window_streams_perturbations(cfg1):
+    """16 perturbations x 8 bands in a 16-slot pool: the window holds 3 Delta psi
+    blocks (2 to fill the slots, 1 whose Delta n is being formed)."""
+    import paper_2203_05623_amd as P
+    s, H, eps, Psi = cfg1
+    dv = workloads.dv_block(CFG, range(16))
+    ref = _oracle_dn(s, H, Psi, eps, dv)
+    ctx = P.sth_create(device=0, max_slots=16)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        dn_w, _, st, res = _run(P, ctx, sid, dv, NV)
+        assert np.all(st == 0) and res.max() <= 1e-12
+        dn_all, _, st2, _ = _run(P, ctx, sid, dv, NV, want_dpsi=True)
+        assert np.all(st2 == 0)
+        assert np.array_equal(dn_w, dn_all), "window changed Delta n"
+        err = np.abs(dn_w - ref).max() / np.abs(ref).max()
+        print(f"window dn vs oracle {err:.2e}")
+        assert err < 1e-10
+    finally:
+        P.sth_destroy(ctx)
+
+
+def _footprint(P, s, Psi, eps, max_slots):
+    """Device memory of the cfg1 system and its slot pool in a fresh context."""
+    ctx = P.sth_create(device=0, max_slots=max_slots)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        return P.sth_system_info_get(ctx, sid)["budget_used"]
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_budget_admits_in_waves_and_refuses_what_never_fits(cfg1):
+    import paper_2203_05623_amd as P
+    s, H, eps, Psi = cfg1
+    npert = 12
+    dv = workloads.dv_block(CFG, range(npert))
+    n3 = CFG.N ** 3
+    blk = NV * s.npw * 16
+    dvb = npert * n3 * 8
+    fixed = npert * n3 * 8 + NV * 4
+    used = _footprint(P, s, Psi, eps, 16)
+    ctx = P.sth_create(device=0, max_slots=16)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        dn_ref, _, _, _ = _run(P, ctx, sid, dv, NV, want_dpsi=True)
+    finally:
+        P.sth_destroy(ctx)
+    # room for dV, dn and one Delta psi block (plus slack below a second block):
+    # the request runs one perturbation at a time
+    budget = used + dvb + fixed + blk + blk // 2
+    ctx = P.sth_create(device=0, max_slots=16, hbm_budget_bytes=budget)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        assert P.sth_system_info_get(ctx, sid)["budget_used"] == used
+        dn, _, st, _ = _run(P, ctx, sid, dv, NV)
+        assert np.all(st == 0)
+        assert np.array_equal(dn, dn_ref), "admission in waves changed Delta n"
+        # keeping every Delta psi block can never fit this budget
+        with pytest.raises(P.SthError) as e:
+            P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-12, want_dpsi=True)
+        assert e.value.code == P.STH_E_NOMEM
+        # nor can a request whose dV and dn alone exceed it
+        big = workloads.dv_block(CFG, range(4 * npert))
+        with pytest.raises(P.SthError) as e:
+            P.sth_submit_solves(ctx, sid, big, np.arange(NV), tol=1e-12)
+        assert e.value.code == P.STH_E_NOMEM
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_queue_full_and_not_ready(cfg1):
+    """One request holds the budget (its solves run to maxit at an unreachable
+    tolerance), a second waits for admission, a third finds the queue full."""
+    import paper_2203_05623_amd as P
+    s, H, eps, Psi = cfg1
+    npert = 8
+    dv = workloads.dv_block(CFG, range(npert))
+    n3 = CFG.N ** 3
+    blk = NV * s.npw * 16
+    dvb = npert * n3 * 8
+    one = npert * n3 * 8 + NV * 4 + blk     # dn, bands and one block
+    used = _footprint(P, s, Psi, eps, 16)
+    # the first request's window (3 blocks) plus dV of two requests, and less
+    # than one more request's smallest footprint
+    budget = used + 2 * dvb + one + 2 * blk + one // 2
+    ctx = P.sth_create(device=0, max_slots=16, hbm_budget_bytes=budget, max_queued=1)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        t1 = P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-300, maxit=400)
+        deadline = time.time() + 30.0
+        while P.sth_poll(ctx, t1)["state"] == 0:   # until the server admits it
+            assert time.time() < deadline
+            time.sleep(0.001)
+        t2 = P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-12)
+        with pytest.raises(P.SthError) as e:
+            P.sth_submit_solves(ctx, sid, dv, np.arange(NV), tol=1e-12)
+        assert e.value.code == P.STH_E_AGAIN
+        info = P.sth_poll(ctx, t2)
+        assert info["state"] == 0, "the second request should wait for the budget"
+        with pytest.raises(P.SthError) as e:
+            P.sth_fetch_drho(ctx, t2, np.empty((npert,) + (CFG.N,) * 3))
+        assert e.value.code == P.STH_E_NOT_READY
+        assert P.sth_wait(ctx, t1, 300.0)
+        _, _, st1, _ = P.sth_fetch_stats(ctx, t1, npert * NV)
+        # none reaches 1e-300: maxit, or breakdown once the recurrence hits rounding
+        assert not np.any(st1 == P.SOLVE_CONVERGED)
+        P.sth_release_ticket(ctx, t1)
+        assert P.sth_wait(ctx, t2, 120.0)
+        it2, res2, st2, _ = P.sth_fetch_stats(ctx, t2, npert * NV)
+        info2 = P.sth_poll(ctx, t2)
+        bad = np.flatnonzero(res2 > 1e-12)
+        print("request 2:", info2, "bad solves", bad, "iters", it2[bad], "resid", res2[bad],
+              "status", st2[bad], "all iters", it2)
+        dn2 = np.empty((npert,) + (CFG.N,) * 3)
+        P.sth_fetch_drho(ctx, t2, dn2)
+        ref = _oracle_dn(s, H, Psi, eps, dv)
+        print("request 2 dn vs oracle", np.abs(dn2 - ref).max() / np.abs(ref).max())
+        assert np.all(st2 == 0) and res2.max() <= 1e-12
+        P.sth_release_ticket(ctx, t2)
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_nan_perturbation_is_isolated(cfg1):
+    import paper_2203_05623_amd as P
+    s, H, eps, Psi = cfg1
+    dv = workloads.dv_block(CFG, range(4))
+    bad = dv.copy()
+    bad[2].reshape(-1)[777] = np.nan
+    ctx = P.sth_create(device=0, max_slots=64)
+    try:
+        sid = _set(P, ctx, s, Psi, eps)
+        dn_ok, x_ok, st_ok, _ = _run(P, ctx, sid, dv, NV, want_dpsi=True)
+        assert np.all(st_ok == 0)
+        for prec in (P.STH_FP64, P.STH_MIXED_BF16):
+            dn, x, st, _ = _run(P, ctx, sid, bad, NV, want_dpsi=True, precision=prec,
+                                tol=1e-12 if prec == P.STH_FP64 else 1e-8)
+            assert np.all(st[2] == P.SOLVE_NAN), st
+            keep = [0, 1, 3]
+            assert np.all(st[keep] == 0), st
+            if prec == P.STH_FP64:
+                assert np.array_equal(x[keep], x_ok[keep])
+                assert np.array_equal(dn[keep], dn_ok[keep])
+            else:
+                err = max(np.linalg.norm(x[j, v] - x_ok[j, v]) / np.linalg.norm(x_ok[j, v])
+                          for j in keep for v in range(NV))
+                assert err < 1e-6
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_served_equals_standalone_on_two_grids(cfg1):
+    """Requests on the 24^3 and 48^3 systems submitted together into one context
+    (and a second request on the 24^3 system sharing its slot pool) give the
+    same bits as each request served alone."""
+    import paper_2203_05623_amd as P
+    s, H, eps, Psi = cfg1
+    cfg4 = workloads.get_config("cfg4a")
+    d = np.load(os.path.join(ROOT, "tests", "oracle_data",
+                             f"cfg4a_seed{cfg4.seed_kb}_valence.npz"))
+    s4 = oracle.build_system("cfg4a")
+    psi4, eps4 = np.ascontiguousarray(d["psi"][:cfg4.nv]), d["eps"][:cfg4.nv]
+    dv1 = workloads.dv_block(CFG, range(6))
+    dv1b = workloads.dv_block(CFG, range(6, 12))
+    dv4 = workloads.dv_block(cfg4, range(2))
+    ctx = P.sth_create(device=0, max_slots=64)
+    try:
+        a = _set(P, ctx, s, Psi, eps)
+        b = _set(P, ctx, s4, psi4, eps4, cfg4)
+        alone1 = _run(P, ctx, a, dv1, NV, want_dpsi=True)
+        alone4 = _run(P, ctx, b, dv4, cfg4.nv, want_dpsi=True)
+        ts = [P.sth_submit_solves(ctx, b, dv4, np.arange(cfg4.nv), tol=1e-12, want_dpsi=True),
+              P.sth_submit_solves(ctx, a, dv1b, np.arange(NV), tol=1e-12),
+              P.sth_submit_solves(ctx, a, dv1, np.arange(NV), tol=1e-12, want_dpsi=True)]
+        for t in ts:
+            assert P.sth_wait(ctx, t, 300.0)
+        x4 = np.empty((2, cfg4.nv, s4.npw), np.complex128)
+        P.sth_fetch_dpsi(ctx, ts[0], x4)
+        x1 = np.empty((6, NV, s.npw), np.complex128)
+        P.sth_fetch_dpsi(ctx, ts[2], x1)
+        dn1 = np.empty((6,) + (CFG.N,) * 3)
+        P.sth_fetch_drho(ctx, ts[2], dn1)
+        dn4 = np.empty((2,) + (cfg4.N,) * 3)
+        P.sth_fetch_drho(ctx, ts[0], dn4)
+        assert np.array_equal(x1, alone1[1]) and np.array_equal(dn1, alone1[0])
+        assert np.array_equal(x4, alone4[1]) and np.array_equal(dn4, alone4[0])
+        for t in ts:
+            P.sth_release_ticket(ctx, t)
+        # and the 48^3 system's solves match the oracle (sampled bands)
+        for j, v in [(0, 0), (1, cfg4.nv - 1)]:
+            bvec = oracle.rhs(s4, psi4, v, dv4[j])
+            ref, _, _, stat = oracle.pcg_solve(s4, psi4, eps4, v, bvec, tol=1e-12)
+            assert stat == 0
+            err = np.linalg.norm(x4[j, v] - ref) / np.linalg.norm(ref)
+            print(f"48^3 solve ({j}, {v}) vs oracle {err:.2e}")
+            assert err < 1e-10
+    finally:
+        P.sth_destroy(ctx)

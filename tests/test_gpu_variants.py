@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_store
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -105,13 +106,10 @@ def test_variants_cfg1(cfg1_system, cfg1_dense, monkeypatch, tmp_path):
 def test_variants_cfg2(monkeypatch, tmp_path):
     import paper_2203_05623_amd as P
     cfg = workloads.get_config("cfg2")
-    cache = os.path.join(ROOT, "tests", "_cache", f"cfg2_seed{cfg.seed_kb}_valence.npz")
-    if not os.path.exists(cache):
-        pytest.skip("oracle valence cache missing: run tests/golden/make_valence_cache.py cfg2")
-    d = np.load(cache)
     s = oracle.build_system("cfg2")
     nv = cfg.nv
-    eps, psi = d["eps"][:nv], d["psi"][:nv]
+    eps, psi = oracle_store.valence("cfg2")
+    eps, psi = eps[:nv], psi[:nv]
     rng = np.random.default_rng(22)
     c = rng.standard_normal((5, s.npw)) + 1j * rng.standard_normal((5, s.npw))
     ref_h = oracle.apply_H(s, c)

@@ -12,6 +12,8 @@ What fixes each result independently of the oracle's own formulas:
   * charge neutrality, linearity, gauge invariance inside a degenerate shell,
     reciprocity (M symmetric) and negative semidefiniteness of chi0.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -80,7 +82,10 @@ def test_pcg_reports_max_iterations(cfg1_setup):
 
 def test_free_electron_closed_form():
     """V = 0, no projectors, valence = the closed shell |m|^2 <= 1 (7 plane waves):
-    Delta psi_v(G) = -dV(G - G_v) / (|G|^2/2 - |G_v|^2/2) for G outside the shell."""
+    Delta psi_v(G) = -dV(G - G_v) / (|G|^2/2 - |G_v|^2/2) for G outside the shell.
+    The oracle's closed form is checked against the expression written out here,
+    against the dense LU solve of the projected equation and against its PCG;
+    a constant potential c shifts H and eps_v alike and leaves it unchanged."""
     s = oracle.build_free_electron_system("cfg1")
     cfg = workloads.get_config("cfg1")
     m = s.miller.astype(int)
@@ -90,19 +95,25 @@ def test_free_electron_closed_form():
     Psi = np.zeros((7, s.npw), complex)
     Psi[np.arange(7), val] = 1.0
     T = kinetic(s)
-    eps = T[val]
     dv = workloads.dv_r(cfg, 3)
     dVG = np.fft.fftn(dv) / s.N ** 3
-    H = oracle.dense_H(s)
-    for v in range(7):
-        d = np.mod(m - m[val[v]], s.N)
-        expect = -dVG[d[:, 0], d[:, 1], d[:, 2]] / (T - eps[v] + (msq <= 1))
-        expect[msq <= 1] = 0.0
-        b = oracle.rhs(s, Psi, v, dv)
-        x = oracle.solve_lu(H, Psi, eps[v], b)
-        assert np.abs(x - expect).max() < 1e-13 * max(1.0, np.abs(expect).max())
-        xp, _, rel, st = oracle.pcg_solve(s, Psi, eps, v, b, tol=1e-12)
-        assert st == 0 and np.linalg.norm(xp - expect) < 1e-10 * np.linalg.norm(expect)
+    for c in (0.0, -0.3):
+        sc = dataclasses.replace(s, vloc_r=np.full_like(s.vloc_r, c))
+        eps = T[val] + c
+        H = oracle.dense_H(sc)
+        for v in range(7):
+            d = np.mod(m - m[val[v]], s.N)
+            expect = -dVG[d[:, 0], d[:, 1], d[:, 2]] / (T - T[val[v]] + (msq <= 1))
+            expect[msq <= 1] = 0.0
+            got = oracle.free_electron_response(sc, val, v, dv)
+            assert np.abs(got - expect).max() < 1e-15 * np.abs(expect).max()
+            b = oracle.rhs(sc, Psi, v, dv)
+            x = oracle.solve_lu(H, Psi, eps[v], b)
+            assert np.abs(x - got).max() < 1e-13 * max(1.0, np.abs(got).max())
+            xp, _, rel, st = oracle.pcg_solve(sc, Psi, eps, v, b, tol=1e-12)
+            assert st == 0 and np.linalg.norm(xp - got) < 1e-10 * np.linalg.norm(got)
+    with pytest.raises(ValueError):   # |m|^2 <= 1 without one of its plane waves
+        oracle.free_electron_response(s, val[:-1], 0, dv)
 
 
 def _density_of(s, H):
