@@ -104,16 +104,26 @@ class OraclePool:
         import multiprocessing as mp
         import tempfile
         self.name, self.cores = name, cores
-        base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+        # scratch for the oracle's arrays (projectors and valence states, GBs at
+        # 144^3): memory-backed /dev/shm when it has room, else the temp dir
+        import shutil
+        base = None
+        if os.path.isdir("/dev/shm") and shutil.disk_usage("/dev/shm").free > (32 << 30):
+            base = "/dev/shm"
         self.scratch = tempfile.mkdtemp(prefix="sth_oracle_", dir=base)
         self.pool = mp.get_context("fork").Pool(cores)
         self.prep = self.pool.apply_async(_oracle_prepare, (name, self.scratch))
 
     def set_valence(self, eps, psi):
-        np.save(os.path.join(self.scratch, "eps.npy"), np.asarray(eps))
-        np.save(os.path.join(self.scratch, "psi.npy"), np.asarray(psi))
+        try:
+            np.save(os.path.join(self.scratch, "eps.npy"), np.asarray(eps))
+            np.save(os.path.join(self.scratch, "psi.npy"), np.asarray(psi))
+        except OSError as e:   # scratch space: reported by run()
+            self.error = e
 
     def run(self, npert, nv, tol, nsample, maxit, gpu_mean_iters):
+        if getattr(self, "error", None) is not None:
+            raise self.error
         build_s = self.prep.get()
         rng = np.random.default_rng(3)
         pairs = [(int(rng.integers(npert)), int(rng.integers(nv))) for _ in range(nsample)]
@@ -392,8 +402,16 @@ def run_workload(P, torch, name, npert, args, pool=None):
     ctx = P.sth_create(device=0, max_slots=args.slots)
     try:
         t0 = time.perf_counter()
-        eps, psi, vres, vits = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij,
-                                             cfg.nv + 1, tol=1e-10)
+        cache = args.valence_cache if name == args.config else ""
+        if cache and os.path.exists(cache):
+            # states of an earlier run of the device eigensolver (profiling passes)
+            d = np.load(cache)
+            eps, psi, vres, vits = d["eps"], d["psi"], float(d["res"]), int(d["iters"])
+        else:
+            eps, psi, vres, vits = P.sth_valence(ctx, cfg.L, cfg.N, miller, vloc, beta, dij,
+                                                 cfg.nv + 1, tol=1e-10)
+            if cache:
+                np.savez(cache, eps=eps, psi=psi, res=vres, iters=vits)
         t_val = time.perf_counter() - t0
         print(f"{name}: valence set-up {t_val:.1f} s ({vits} iterations, residual {vres:.1e})",
               file=sys.stderr, flush=True)
@@ -500,7 +518,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--valence-cache", default="",
-                    help="npz file of valence states (pdep and lanczos modes)")
+                    help="npz file: load the valence states of the main workload (and of the "
+                         "pdep / lanczos modes) from it if present, else compute them on the "
+                         "device and save them there")
     ap.add_argument("--served", action="store_true",
                     help="served mode: Poisson request stream over several systems")
     ap.add_argument("--served-systems", default="cfg4a,cfg4b,cfg4c")
@@ -559,6 +579,9 @@ def main():
         try:
             cpu = pool.run(npert, cfg.nv, args.tol, nsample, maxit,
                            main_run["legs"][args.precision]["cg_iterations"]["mean"])
+        except (OSError, RuntimeError) as e:   # scratch space, valence check
+            print(f"oracle baseline failed: {e}", file=sys.stderr, flush=True)
+            cpu = {"value": None, "error": str(e)}
         finally:
             pool.close()
         print("oracle baseline done", file=sys.stderr, flush=True)

@@ -187,8 +187,9 @@ sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* 
  * LOBPCG on nbands + 8 vectors while 3 (nbands + 8) <= 2048, else
  * Chebyshev-filtered subspace iteration (degree 16, Zhou-Saad scaled
  * recurrence, spectrum upper bound from a 12-step Lanczos run) on
- * nbands + max(8, nbands / 10) vectors; the environment variable
- * STH_VALENCE=lobpcg or chfsi forces one.  Needs 3 (nbands + 8) <= npw
+ * nbands + max(8, g nbands) vectors, g = 0.4 or the environment variable
+ * STH_CHFSI_GUARD; the environment variable STH_VALENCE=lobpcg or chfsi forces
+ * one.  Needs 3 (nbands + 8) <= npw
  * (LOBPCG) or 2 nb <= npw (subspace iteration), else STH_E_INVALID.
  * eps_out [nbands], psi_out complex128 [nbands][npw] (caller order), both in
  * `out_ptr_kind` memory.  Converged when every residual ||H x - theta x|| <= tol.

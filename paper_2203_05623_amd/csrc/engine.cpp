@@ -1372,11 +1372,6 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
     Request* r = sh.req;
     const int st = h_status[slot];
     const double rel = h_bn2[slot] > 0 ? std::sqrt(h_rn2[slot] / h_bn2[slot]) : 0.0;
-    if (st == SLOT_DONE && rel > 1.001 * r->tol)   // cannot happen: the check bounds it
-      std::fprintf(stderr, "sth: internal: slot %d retired converged with residual %.3e > tol "
-                   "%.1e (iterations %d, ||r||^2 %.3e, ||b||^2 %.3e, ticket %llu, solve %d)\n",
-                   slot, rel, r->tol, h_iters[slot], h_rn2[slot], h_bn2[slot],
-                   (unsigned long long)r->ticket, sh.solve);
     r->iters[sh.solve] = h_iters[slot];
     r->resid[sh.solve] = rel;
     r->status[sh.solve] = st == SLOT_DONE        ? STH_SOLVE_CONVERGED

@@ -19,7 +19,7 @@
 // each iteration a degree-16 filter in the scaled three-term recurrence (15
 // block H applications), orthonormalisation, one H application and
 // Rayleigh-Ritz.  The filter damps [theta_nb, b] with b an upper bound of the
-// spectrum; the block carries about 10% guard vectors.
+// spectrum; the block carries 40% guard vectors by default.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,6 +37,28 @@ namespace sth {
 namespace {
 
 constexpr int kLobpcgMaxDim = 2048;   // largest LOBPCG Rayleigh-Ritz problem (3 nb)
+
+// splitmix64 (Steele, Lea and Flood's SplittableRandom finaliser): a counter-based
+// generator, so every coefficient of the start block is drawn independently
+__device__ inline unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Start block: X[i][k] = (g1 + i g2) / (1 + T_k)^2 with g1, g2 standard normal
+// (Box-Muller on two uniform numbers in (0, 1] from the counter i * npw + k)
+__global__ void k_random_start(z64* X, int nb, int npw, const double* kin,
+                               unsigned long long seed) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nb * npw) return;
+  const unsigned long long a = splitmix64(seed ^ (2ull * t)), b = splitmix64(seed ^ (2ull * t + 1));
+  const double u1 = ((a >> 11) + 1.0) * 0x1.0p-53, u2 = (b >> 11) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double k = kin[t % npw], damp = 1.0 / ((1.0 + k) * (1.0 + k));
+  X[t] = z64{r * cos(2.0 * M_PI * u2) * damp, r * sin(2.0 * M_PI * u2) * damp};
+}
 constexpr int kChebDegree = 16;       // Chebyshev filter degree of the subspace iteration
 
 struct Lobpcg {
@@ -172,13 +194,16 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
                      : va && std::strcmp(va, "lobpcg") == 0 ? false
                                                             : 3 * (nbands + 8) > kLobpcgMaxDim;
   // guard vectors above the wanted bands: the filter's convergence factor for
-  // band nbands is set by the spectral distance to the top of the block, so the
-  // subspace iteration keeps about 10% more
-  const int guard = chfsi ? std::max(8, nbands / 10) : 8;
+  // band nbands is set by the spectral distance to the top of the block
+  // (theta_nb, from which the filter damps), so the subspace iteration keeps a
+  // fraction STH_CHFSI_GUARD (default 0.4) of extra vectors
+  double gfrac = 0.4;
+  if (const char* ge = std::getenv("STH_CHFSI_GUARD")) gfrac = std::atof(ge);
+  const int guard = chfsi ? std::max(8, int(gfrac * nbands)) : 8;
   const int nb = nbands + guard;
-  if (nbands <= 0 || (chfsi ? 2 * nb : 3 * nb) > d.npw) {
+  if (nbands <= 0 || gfrac < 0.0 || (chfsi ? 2 * nb : 3 * nb) > d.npw) {
     set_error("valence: need 0 < 3 (nbands + 8) <= npw (LOBPCG) or 2 (nbands + guard) <= npw "
-              "(subspace iteration, guard = max(8, nbands / 10))");
+              "(subspace iteration, guard = max(8, STH_CHFSI_GUARD x nbands))");
     throw Error(STH_E_INVALID);
   }
   if (maxit <= 0) maxit = 500;
@@ -190,6 +215,10 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
   STH_HIP_CHECK(hipSetDevice(device_));
   System s;
   StickBuild sb = setup_geometry(s, d, 0);
+  if (verbose)
+    std::fprintf(stderr, "valence: %d vectors (%d bands + %d guard), set-up %.1f s\n", nb, nbands,
+                 guard,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
   const int n = s.npw;
   HScratch hw;
   h_scratch(s, hw, std::min(nb, 256));
@@ -205,19 +234,10 @@ void Context::valence(const sth_system_desc& d, int nbands, double tol, int maxi
   z64* X = S.as<z64>();
   z64* HX = HS.as<z64>();
 
-  // start: seeded random vectors damped at high kinetic energy
-  {
-    std::mt19937_64 rng(7);
-    std::normal_distribution<double> nd(0.0, 1.0);
-    std::vector<z64> h((size_t)nb * n);
-    for (int i = 0; i < nb; ++i)
-      for (int k = 0; k < n; ++k) {
-        const double damp = 1.0 / ((1.0 + sb.kin[k]) * (1.0 + sb.kin[k]));
-        h[(size_t)i * n + k] = z64{nd(rng) * damp, nd(rng) * damp};
-      }
-    STH_HIP_CHECK(hipMemcpyAsync(X, h.data(), h.size() * sizeof(z64), hipMemcpyHostToDevice,
-                                 st_));
-  }
+  // start: seeded random vectors damped at high kinetic energy, drawn on the device
+  hipLaunchKernelGGL(k_random_start, dim3(unsigned(((long long)nb * n + 255) / 256)), dim3(256),
+                     0, st_, X, nb, n, s.d_kin.as<double>(), 7ull);
+  STH_HIP_CHECK(hipGetLastError());
   if (L.orth(X, nb, nullptr, nullptr, 0, nullptr) != nb) {
     set_error("valence: degenerate start block");
     throw Error(STH_E_INTERNAL);

@@ -106,9 +106,13 @@ def _footprint(P, s, Psi, eps, max_slots):
         P.sth_destroy(ctx)
 
 
-def test_budget_admits_in_waves_and_refuses_what_never_fits(cfg1):
+def test_budget_admits_in_waves_and_refuses_what_never_fits(cfg1, monkeypatch, tmp_path):
     import paper_2203_05623_amd as P
     s, H, eps, Psi = cfg1
+    # the contexts below share one tuning (the autotuner's picks follow timings,
+    # and another FFT variant rounds differently), so their results compare bit
+    # for bit
+    monkeypatch.setenv("STH_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     npert = 12
     dv = workloads.dv_block(CFG, range(npert))
     n3 = CFG.N ** 3
@@ -184,15 +188,13 @@ def test_queue_full_and_not_ready(cfg1):
         P.sth_release_ticket(ctx, t1)
         assert P.sth_wait(ctx, t2, 120.0)
         it2, res2, st2, _ = P.sth_fetch_stats(ctx, t2, npert * NV)
-        info2 = P.sth_poll(ctx, t2)
-        bad = np.flatnonzero(res2 > 1e-12)
-        print("request 2:", info2, "bad solves", bad, "iters", it2[bad], "resid", res2[bad],
-              "status", st2[bad], "all iters", it2)
+        assert np.all(st2 == 0) and res2.max() <= 1e-12
         dn2 = np.empty((npert,) + (CFG.N,) * 3)
         P.sth_fetch_drho(ctx, t2, dn2)
         ref = _oracle_dn(s, H, Psi, eps, dv)
-        print("request 2 dn vs oracle", np.abs(dn2 - ref).max() / np.abs(ref).max())
-        assert np.all(st2 == 0) and res2.max() <= 1e-12
+        err = np.abs(dn2 - ref).max() / np.abs(ref).max()
+        print(f"request admitted after the queue drained: dn vs oracle {err:.2e}")
+        assert err < 1e-10
         P.sth_release_ticket(ctx, t2)
     finally:
         P.sth_destroy(ctx)
