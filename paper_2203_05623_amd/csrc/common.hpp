@@ -38,19 +38,26 @@ __host__ __device__ inline cpx<T> mul_i(cpx<T> a) {
 }
 
 // Workgroups are dispatched to the chip's 8 XCDs round-robin by linear id, and
-// each XCD has its own L2.  The logical tile (x, y, z) of a workgroup is taken
-// so that every XCD gets one contiguous range of logical ids in x-fastest
-// order: tiles that share an operand along x run on one XCD, one after the
-// other.  A bijection of the grid for any size.
-__device__ inline void xcd_tile3(int& x, int& y, int& z) {
-  const long long gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-  const long long T = gx * gy * gz;
-  const long long L = blockIdx.x + gx * (blockIdx.y + gy * (long long)blockIdx.z);
-  const long long q = T / 8, r = T % 8, xcd = L % 8, j = L / 8;
+// each XCD has its own L2 (the 256 MB last-level cache is shared).  xcd_tile2
+// maps the workgroups of one (x, y) slice of the grid so that every XCD gets
+// one contiguous range of logical tiles, x fastest (or y fastest): tiles that
+// share an operand along the fast index run on one XCD, one after the other,
+// while z (the K-chunk of a split-K product) stays the slowest index of the
+// dispatch order, so that all XCDs work on the same chunk at a time.  A
+// bijection of each slice for any size.
+__device__ inline void xcd_tile2(bool yfast, int& x, int& y) {
+  const long long gx = gridDim.x, gy = gridDim.y;
+  const long long S = gx * gy;
+  const long long L = blockIdx.x + gx * (long long)blockIdx.y;
+  const long long q = S / 8, r = S % 8, xcd = L % 8, j = L / 8;
   const long long lg = xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
-  x = int(lg % gx);
-  y = int((lg / gx) % gy);
-  z = int(lg / (gx * gy));
+  if (yfast) {
+    y = int(lg % gy);
+    x = int(lg / gy);
+  } else {
+    x = int(lg % gx);
+    y = int(lg / gx);
+  }
 }
 
 }  // namespace sth

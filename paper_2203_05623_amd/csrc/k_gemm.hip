@@ -16,6 +16,8 @@
 //   D[i][j], register v: j = l % 16 and
 //     i = l / 16 + 4 v      for v_mfma_f64_16x16x4f64,
 //     i = 4 (l / 16) + v    for v_mfma_f32_16x16x4f32.
+#include <cstdlib>
+
 #include "errors.hpp"
 #include "kernels.hpp"
 
@@ -56,39 +58,51 @@ template <typename T>
 constexpr int gemm_wpe() { return sizeof(T) == 8 ? 3 : 4; }
 
 // part[s][c][m] = sum_{k in chunk s} conj(A[m][k]) B_c[k]   (accumulated in T)
-template <typename T, typename TB>
-__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T>()))) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
+// Workgroup tile: 64 rows of A x 32 NY columns of B; the 4 waves sit 2 x 2, each
+// holding 32 rows x 16 NY columns (2 x NY MFMA tiles, real and imaginary parts).
+// NY = 4 (128 columns) halves the re-reads of A per column of B against NY = 2.
+template <typename T, typename TB, int NY>
+__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? gemm_wpe<T>() : 2))) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
                                                     VecSet<const TB> B, const int* slots,
                                                     int ncols, int K, int kchunk, cpx<T>* part) {
   using V4 = typename Mfma<T>::v4;
+  constexpr int CT = 32 * NY;             // columns of the workgroup tile
+  constexpr int NB = CT * GK / GTHR;      // staged B elements per thread
   __shared__ cpx<T> As[GT][GK + 1];
-  __shared__ cpx<T> Bs[GT][GK + 1];
+  __shared__ cpx<T> Bs[CT][GK + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  int tx, ty, s;
-  xcd_tile3(tx, ty, s);   // the m-tiles sharing a block of vectors run on one XCD
-  const int m0 = tx * GT, n0 = ty * GT;
+  // one K-chunk at a time over the whole chip; within it, the m-tiles that share
+  // a block of vectors run on one XCD
+  int tx, ty;
+  xcd_tile2(false, tx, ty);
+  const int s = blockIdx.z;
+  const int m0 = tx * GT, n0 = ty * CT;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
-  V4 accr[2][2], acci[2][2];
+  V4 accr[2][NY], acci[2][NY];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
-  const TB* brow[4];
+    for (int b = 0; b < NY; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
+  const TB* brow[NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const int n = n0 + (tid + i * GTHR) / GK;
     brow[i] = (n < ncols) ? B.base + (long long)slots[n] * B.stride : nullptr;
   }
   const int kq = lane >> 4, r16 = lane & 15;
   // the next K-tile is fetched into registers while the current one is multiplied
-  cpx<T> ra[4], rb[4];
+  cpx<T> ra[4], rb[NB];
   auto fetch = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK, k = kb + c;
       const int m = m0 + row;
       ra[i] = (m < M && k < kend) ? A[(long long)m * lda + k] : cpx<T>{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int idx = tid + i * GTHR, c = idx % GK, k = kb + c;
       rb[i] = (brow[i] && k < kend) ? rnd<T>(brow[i][k]) : cpx<T>{0, 0};
     }
   };
@@ -96,9 +110,13 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
   for (int kb = kbeg; kb < kend; kb += GK) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int idx = tid + i * GTHR, row = idx / GK, c = idx % GK;
-      As[row][c] = ra[i];
-      Bs[row][c] = rb[i];
+      const int idx = tid + i * GTHR;
+      As[idx / GK][idx % GK] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int idx = tid + i * GTHR;
+      Bs[idx / GK][idx % GK] = rb[i];
     }
     __syncthreads();
     if (kb + GK < kend) fetch(kb + GK);
@@ -106,19 +124,22 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int c = 2 * kk + (kq >> 1);
       const bool im = kq & 1;
-      T a[2], br[2], bi[2];
+      T a[2], br[NY], bi[NY];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const cpx<T> w = As[wm * 32 + t * 16 + r16][c];
         a[t] = im ? w.y : w.x;
-        const cpx<T> z = Bs[wn * 32 + t * 16 + r16][c];
+      }
+#pragma unroll
+      for (int t = 0; t < NY; ++t) {
+        const cpx<T> z = Bs[wn * 16 * NY + t * 16 + r16][c];
         br[t] = im ? z.y : z.x;
         bi[t] = im ? -z.x : z.y;
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int y = 0; y < NY; ++y) {
           accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
           acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
         }
@@ -128,11 +149,11 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < NY; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm * 32 + x * 16 + Mfma<T>::row(kq, v);
-        const int n = n0 + wn * 32 + y * 16 + r16;
+        const int n = n0 + wn * 16 * NY + y * 16 + r16;
         if (m < M && n < ncols)
           part[((long long)s * ncols + n) * M + m] = cpx<T>{accr[x][y][v], acci[x][y][v]};
       }
@@ -159,41 +180,48 @@ __global__ void k_reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M,
 }
 
 // Y_c[g] = s0 Y_c[g] + sum_m A[m][g] C[c][m]  (+ optional partial dots with dot_in).
+// Workgroup tile: 64 rows g x 32 NY columns; each wave 32 g x 16 NY columns.
 // The FP64 register budget for three workgroups per CU measured 55 TFLOP/s
 // against 48 with the compiler's two-workgroup default.
-template <typename T>
-__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T>()))) void k_gemm_a_c(
+template <typename T, int NY>
+__global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? gemm_wpe<T>() : 2))) void k_gemm_a_c(
     const cpx<T>* __restrict__ A, int lda, int M, const cpx<T>* __restrict__ C, VecSet<z64> Y,
     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots) {
   using V4 = typename Mfma<T>::v4;
+  constexpr int CT = 32 * NY;             // columns of the workgroup tile
+  constexpr int NC = CT * GK / GTHR;      // staged C elements per thread
   __shared__ cpx<T> Ws[GK][GT + 1];
-  __shared__ cpx<T> Cs[GT][GK + 1];
-  __shared__ double red[2][GT];
+  __shared__ cpx<T> Cs[CT][GK + 1];
+  __shared__ double red[CT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = wave & 1, wn = wave >> 1;
-  const int g0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  // the column tiles that share a block of W rows run on one XCD, one after the
+  // other, so that block is read from memory once
+  int tx, ty;
+  xcd_tile2(true, tx, ty);
+  const int g0 = tx * GT, n0 = ty * CT;
   const int kq = lane >> 4, r16 = lane & 15;
-  V4 accr[2][2], acci[2][2];
+  V4 accr[2][NY], acci[2][NY];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
+    for (int b = 0; b < NY; ++b) accr[a][b] = acci[a][b] = V4{0, 0, 0, 0};
   // the next M-tile of W and C is fetched into registers during the multiply
-  cpx<T> rw[4], rc[4];
+  cpx<T> rw[4], rc[NC];
   auto fetch = [&](int mb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR;
-      {
-        const int mr = idx / GT, gc = idx % GT;
-        const int m = mb + mr, gg = g0 + gc;
-        rw[i] = (m < M && gg < K) ? A[(long long)m * lda + gg] : cpx<T>{0, 0};
-      }
-      {
-        const int nr = idx / GK, mc = idx % GK;
-        const int n = n0 + nr, m = mb + mc;
-        rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : cpx<T>{0, 0};
-      }
+      const int mr = idx / GT, gc = idx % GT;
+      const int m = mb + mr, gg = g0 + gc;
+      rw[i] = (m < M && gg < K) ? A[(long long)m * lda + gg] : cpx<T>{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int idx = tid + i * GTHR;
+      const int nr = idx / GK, mc = idx % GK;
+      const int n = n0 + nr, m = mb + mc;
+      rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : cpx<T>{0, 0};
     }
   };
   if (M > 0) fetch(0);
@@ -202,6 +230,10 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + i * GTHR;
       Ws[idx / GT][idx % GT] = rw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int idx = tid + i * GTHR;
       Cs[idx / GK][idx % GK] = rc[i];
     }
     __syncthreads();
@@ -210,19 +242,22 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int mm = 2 * kk + (kq >> 1);
       const bool im = kq & 1;
-      T a[2], br[2], bi[2];
+      T a[2], br[NY], bi[NY];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const cpx<T> w = Ws[mm][wg * 32 + t * 16 + r16];
         a[t] = im ? w.y : w.x;
-        const cpx<T> c = Cs[wn * 32 + t * 16 + r16][mm];
+      }
+#pragma unroll
+      for (int t = 0; t < NY; ++t) {
+        const cpx<T> c = Cs[wn * 16 * NY + t * 16 + r16][mm];
         br[t] = im ? -c.y : c.x;
         bi[t] = im ? c.x : c.y;
       }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int y = 0; y < NY; ++y) {
           if constexpr (sizeof(T) == 4) {   // transposed tile: column index in the rows
             accr[x][y] = Mfma<T>::op(br[y], a[x], accr[x][y]);
             acci[x][y] = Mfma<T>::op(bi[y], a[x], acci[x][y]);
@@ -238,12 +273,16 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
     // FP32: the tile is held transposed, D[n][g] with n = 4 (l / 16) + v and
     // g = l % 16, so that one store instruction writes 16 consecutive g of each
     // of 4 columns (256 B runs) instead of 16 B pieces 64 B apart
-    double dsum[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    double dsum[NY][4];
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < NY; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dsum[y][v] = 0.0;
+#pragma unroll
+    for (int y = 0; y < NY; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int n = n0 + wn * 32 + y * 16 + 4 * kq + v;
+        const int n = n0 + wn * 16 * NY + y * 16 + 4 * kq + v;
         if (n >= ncols) continue;
         z64* yrow = Y.base + (long long)slots[n] * Y.stride;
         const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
@@ -268,35 +307,36 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
     if (!dots) return;
     // sum over the 16 lanes that share a column, then over the two g halves
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < NY; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) dsum[y][v] += __shfl_xor(dsum[y][v], o);
-    double* redf = &red[0][0];   // [GT] column sums of the wg == 1 half
-    if (wg == 1 && r16 == 0) {
+    if (wg == 1 && r16 == 0) {   // column sums of the wg == 1 half
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < NY; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) redf[wn * 32 + y * 16 + 4 * kq + v] = dsum[y][v];
+        for (int v = 0; v < 4; ++v) red[wn * 16 * NY + y * 16 + 4 * kq + v] = dsum[y][v];
     }
     __syncthreads();
     if (wg == 0 && r16 == 0) {
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < NY; ++y)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int c = wn * 32 + y * 16 + 4 * kq + v;
+          const int c = wn * 16 * NY + y * 16 + 4 * kq + v;
           const int n = n0 + c;
-          if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y][v] + redf[c];
+          if (n < ncols) dots[(long long)n * gridDim.x + tx] = dsum[y][v] + red[c];
         }
     }
     return;
   }
-  double dsum[2] = {0.0, 0.0};
+  double dsum[NY];
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    const int n = n0 + wn * 32 + y * 16 + r16;
+  for (int y = 0; y < NY; ++y) dsum[y] = 0.0;
+#pragma unroll
+  for (int y = 0; y < NY; ++y) {
+    const int n = n0 + wn * 16 * NY + y * 16 + r16;
     if (n >= ncols) continue;
     z64* yrow = Y.base + (long long)slots[n] * Y.stride;
     const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
@@ -323,22 +363,33 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(gemm_wpe<T
   if (!dots) return;
   // sum over the 4 lane groups that share a column, then over the two g halves
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
+  for (int y = 0; y < NY; ++y) {
     dsum[y] += __shfl_xor(dsum[y], 16);
     dsum[y] += __shfl_xor(dsum[y], 32);
   }
   if (wg == 1 && kq == 0) {
-    red[0][wn * 32 + r16] = dsum[0];
-    red[1][wn * 32 + r16] = dsum[1];
+#pragma unroll
+    for (int y = 0; y < NY; ++y) red[wn * 16 * NY + y * 16 + r16] = dsum[y];
   }
   __syncthreads();
   if (wg == 0 && kq == 0) {
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int n = n0 + wn * 32 + y * 16 + r16;
-      if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y] + red[y][wn * 32 + r16];
+    for (int y = 0; y < NY; ++y) {
+      const int c = wn * 16 * NY + y * 16 + r16;
+      const int n = n0 + c;
+      if (n < ncols) dots[(long long)n * gridDim.x + tx] = dsum[y] + red[c];
     }
   }
+}
+
+// Column tile of both GEMMs: 128 columns once there are enough columns to fill
+// them (STH_GEMM_NY=2 keeps 64)
+int gemm_ny() {
+  static const int ny = [] {
+    const char* e = std::getenv("STH_GEMM_NY");
+    return e ? std::atoi(e) : 4;
+  }();
+  return ny;
 }
 
 template <typename T>
@@ -346,9 +397,15 @@ void gemm_ah_b(const cpx<T>* A, int lda, int M, VecSet<const z64> B, const int* 
                int K, int kchunk, cpx<T>* part, hipStream_t st) {
   if (ncols <= 0 || M <= 0) return;
   const int nsplit = (K + kchunk - 1) / kchunk;
-  dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
-  hipLaunchKernelGGL((k_gemm_ah_b<T, z64>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots, ncols,
-                     K, kchunk, part);
+  if (gemm_ny() == 4 && ncols >= 256) {
+    dim3 grid((M + GT - 1) / GT, (ncols + 127) / 128, nsplit);
+    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 4>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
+                       ncols, K, kchunk, part);
+  } else {
+    dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
+    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 2>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
+                       ncols, K, kchunk, part);
+  }
   STH_HIP_CHECK(hipGetLastError());
 }
 
@@ -367,9 +424,15 @@ void gemm_a_c(const cpx<T>* A, int lda, int M, const cpx<T>* C, VecSet<z64> Y, c
               int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots,
               hipStream_t st) {
   if (ncols <= 0) return;
-  dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
-  hipLaunchKernelGGL((k_gemm_a_c<T>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols, K,
-                     s0, dot_in, dots);
+  if (gemm_ny() == 4 && ncols >= 256) {
+    dim3 grid(gemm_a_c_tiles(K), (ncols + 127) / 128);
+    hipLaunchKernelGGL((k_gemm_a_c<T, 4>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols,
+                       K, s0, dot_in, dots);
+  } else {
+    dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
+    hipLaunchKernelGGL((k_gemm_a_c<T, 2>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols,
+                       K, s0, dot_in, dots);
+  }
   STH_HIP_CHECK(hipGetLastError());
 }
 

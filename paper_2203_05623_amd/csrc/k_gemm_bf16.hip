@@ -75,8 +75,11 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
   __shared__ bz Bs[2][BT][BKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  int tx, ty, s;
-  xcd_tile3(tx, ty, s);   // the m-tiles sharing a block of vectors run on one XCD
+  // one K-chunk at a time over the whole chip; within it, the m-tiles that share
+  // a block of vectors run on one XCD
+  int tx, ty;
+  xcd_tile2(false, tx, ty);
+  const int s = blockIdx.z;
   const int m0 = tx * BT, n0 = ty * BT;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
   const int kq = lane >> 4, r16 = lane & 15;
@@ -170,7 +173,11 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
   __shared__ double red[2][BT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = wave & 1, wn = wave >> 1;
-  const int g0 = blockIdx.x * BT, n0 = blockIdx.y * BT;
+  // the column tiles that share a block of W rows run on one XCD, one after the
+  // other, so that block is read from memory once
+  int tx, ty;
+  xcd_tile2(true, tx, ty);
+  const int g0 = tx * BT, n0 = ty * BT;
   const int kq = lane >> 4, r16 = lane & 15;
   f4 accr[2][2], acci[2][2];
 #pragma unroll
@@ -279,7 +286,7 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       const int n = n0 + wn * 32 + y * 16 + r16;
-      if (n < ncols) dots[(long long)n * gridDim.x + blockIdx.x] = dsum[y] + red[y][wn * 32 + r16];
+      if (n < ncols) dots[(long long)n * gridDim.x + tx] = dsum[y] + red[y][wn * 32 + r16];
     }
   }
 }
