@@ -182,6 +182,20 @@ sth_status sth_release_system(sth_ctx* ctx, int32_t system_id);
 sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* in,
                        double* out, int ptr_kind, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same product as
+ * sth_apply_h, out = H in for nvec vectors (complex128 [nvec][npw], caller's
+ * order), both in DEVICE memory of the context's GPU, enqueued on `stream`
+ * (NULL = default stream) without synchronising and without any allocation.
+ * The work space is one static device array of 64 MiB per GPU, held until the
+ * process ends (vectors are taken in chunks that fit it); a system whose single
+ * vector needs more work space than that is refused with STH_E_INVALID.  Every
+ * call on a GPU shares the array: calls that overlap on one GPU (different
+ * streams, threads or contexts) race and must be ordered by the caller.  The
+ * system must stay resident until the enqueued work has run. */
+sth_status sth_apply_h_noalloc(sth_ctx* ctx, int32_t system_id, int nvec, const double* in,
+                               double* out, void* stream);
+
 /* Lowest nbands eigenpairs of H for a system description whose psi_v / eps_v
  * are ignored (nv may be 0), on the device with FP64 Rayleigh-Ritz: block
  * LOBPCG on nbands + 8 vectors while 3 (nbands + 8) <= 2048, else

@@ -23,6 +23,7 @@ STH_FP64, STH_MIXED, STH_MIXED_BF16 = 0, 1, 2
 SOLVE_CONVERGED, SOLVE_MAXIT, SOLVE_BREAKDOWN, SOLVE_NAN = 0, 1, 2, 3
 
 EXPORTS = ["sth_create", "sth_destroy", "sth_set_system", "sth_release_system", "sth_apply_h",
+           "sth_apply_h_noalloc",
            "sth_valence", "sth_submit_solves", "sth_poll", "sth_wait", "sth_fetch_drho",
            "sth_fetch_dpsi", "sth_fetch_stats", "sth_chi0_block", "sth_release_ticket",
            "sth_profile", "sth_profile_read", "sth_system_info_get", "sth_pdep", "sth_lanczos",
@@ -97,6 +98,7 @@ def load():
         "sth_profile": [vp, C.c_int],
         "sth_profile_read": [vp, vp, vp, vp, vp],
         "sth_system_info_get": [vp, i32, C.POINTER(sth_system_info)],
+        "sth_apply_h_noalloc": [vp, i32, C.c_int, vp, vp, vp],
         "sth_pdep": [vp, i32, C.c_int, C.c_int, dbl, C.c_int, dbl, C.c_int, vp, vp, C.c_int, vp,
                      C.POINTER(C.c_int), C.POINTER(dbl)],
         "sth_lanczos": [vp, i32, C.c_int, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp],
@@ -252,6 +254,19 @@ def sth_apply_h(ctx, system_id, c, out=None):
     if kin != kout:
         raise ValueError("in and out must live on the same side")
     _check(lib().sth_apply_h(ctx, system_id, nvec, pin, pout, kin, _stream(c)))
+    return out
+
+
+def sth_apply_h_noalloc(ctx, system_id, c, out):
+    """H c without allocation: c and out are torch CUDA tensors (complex128
+    [nvec, npw], caller's order); enqueued on torch's current stream."""
+    if not (_is_torch(c) and _is_torch(out)):
+        raise ValueError("sth_apply_h_noalloc takes device (torch CUDA) tensors only")
+    npw = sth_system_info_get(ctx, system_id)["npw"]
+    nvec = int(c.shape[0])
+    pin, _, k1 = _ptr(c, np.complex128, nvec * npw, "c")
+    pout, _, k2 = _ptr(out, np.complex128, nvec * npw, "out", out=True)
+    _check(lib().sth_apply_h_noalloc(ctx, system_id, nvec, pin, pout, _stream(c)))
     return out
 
 

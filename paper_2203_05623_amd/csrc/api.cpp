@@ -110,6 +110,13 @@ sth_status sth_apply_h(sth_ctx* ctx, int32_t system_id, int nvec, const double* 
   });
 }
 
+sth_status sth_apply_h_noalloc(sth_ctx* ctx, int32_t system_id, int nvec, const double* in,
+                               double* out, void* stream) {
+  return guard([&] {
+    ctx_of(ctx)->apply_h_noalloc(system_id, nvec, in, out, static_cast<hipStream_t>(stream));
+  });
+}
+
 sth_status sth_valence(sth_ctx* ctx, const sth_system_desc* desc, int nbands, double tol,
                        int maxit, double* eps_out, double* psi_out, int out_ptr_kind,
                        double* max_resid, int* iters) {

@@ -135,6 +135,7 @@ Context::Context(const sth_config& cfg)
   size_t lim = cfg.hbm_budget_bytes ? cfg.hbm_budget_bytes : size_t(0.9 * double(fr));
   budget_.set_limit(lim);
   STH_HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+  noalloc_init(device_);   // device address of the allocation-free entry point's array
   // STH_GRAPHS=0 turns the captured-iteration replay off (direct launches)
   if (const char* e = std::getenv("STH_GRAPHS")) use_graphs_ = std::atoi(e) != 0;
   server_ = std::thread([this] { server_loop(); });
@@ -787,24 +788,35 @@ void Context::h_scratch(System& s, HScratch& w, int cap) {
 // out = H in for n contiguous vectors (internal order): T + V_loc by the
 // dual-space FFT route, V_NL by the projector GEMMs.
 void Context::h_block(System& s, HScratch& w, const z64* in, z64* out, int n) {
+  HView v;
+  v.sticks = w.sticks.as<z64>();
+  v.part = w.part.as<z64>();
+  v.C = w.C.as<z64>();
+  v.zeros = w.zeros.as<double>();
+  v.ids = w.ids.as<int>();
+  v.cap = w.cap;
+  h_block_on(s, v, in, out, n, st_);
+}
+
+void Context::h_block_on(System& s, const HView& w, const z64* in, z64* out, int n,
+                         hipStream_t st_) {
   const int N = s.N;
   for (int c0 = 0; c0 < n; c0 += w.cap) {
     const int nc = std::min(w.cap, n - c0);
     VecSet<const z64> vin{in + (size_t)c0 * s.npw, (long long)s.npw};
     VecSet<z64> vout{out + (size_t)c0 * s.npw, (long long)s.npw};
-    VecSet<z64> st{w.sticks.as<z64>(), (long long)N * s.nst};
-    const int* ids = w.ids.as<int>();
+    VecSet<z64> st{w.sticks, (long long)N * s.nst};
+    const int* ids = w.ids;
     launch_zfft_inv<double, z64>(s.g, vin, st, ids, nc, st_);
     launch_plane_local<double>(s.g, st, ids, nc, s.d_vloc.as<double>(), nullptr, st_);
-    launch_zfft_fwd<double, z64>(s.g, {st.base, st.stride}, vout, ids, nc, ZF_SHIFT, vin,
-                                 w.zeros.as<double>(), st_);
+    launch_zfft_fwd<double, z64>(s.g, {st.base, st.stride}, vout, ids, nc, ZF_SHIFT, vin, w.zeros,
+                                 st_);
     if (s.nproj) {
-      launch_gemm_ah_b(s.beta(), s.npw, s.nproj, vin, ids, nc, s.npw, s.kchunk,
-                       w.part.as<z64>(), st_);
-      launch_reduce_parts(w.part.as<z64>(), s.nsplit, nc, s.nproj, s.d_diag.as<double>() + s.nv,
-                          1.0, w.C.as<z64>(), st_);
-      launch_gemm_a_c(s.beta(), s.npw, s.nproj, w.C.as<z64>(), vout, ids, nc, s.npw, 1.0,
-                      {nullptr, 0}, nullptr, st_);
+      launch_gemm_ah_b(s.beta(), s.npw, s.nproj, vin, ids, nc, s.npw, s.kchunk, w.part, st_);
+      launch_reduce_parts(w.part, s.nsplit, nc, s.nproj, s.d_diag.as<double>() + s.nv, 1.0, w.C,
+                          st_);
+      launch_gemm_a_c(s.beta(), s.npw, s.nproj, w.C, vout, ids, nc, s.npw, 1.0, {nullptr, 0},
+                      nullptr, st_);
     }
   }
 }

@@ -33,6 +33,11 @@ inline int split_chunk(int K, int nsplit) {
 
 double now_s();
 
+// Static device work space of the allocation-free entry point (noalloc.cpp):
+// its address on the current device is taken once per device at context creation.
+void noalloc_init(int device);
+size_t noalloc_capacity();
+
 // Owning device allocation, charged against the context's HBM budget.
 class Budget;
 class DevMem {
@@ -287,7 +292,18 @@ class Context {
     DevMem sticks, part, C, zeros, ids;
     int cap = 0;
   };
+  // non-owning view of an H work space (the HScratch buffers, or the static
+  // array of the allocation-free entry point)
+  struct HView {
+    z64 *sticks = nullptr, *part = nullptr, *C = nullptr;
+    double* zeros = nullptr;
+    int* ids = nullptr;
+    int cap = 0;
+  };
   void h_block(System& s, HScratch& w, const z64* in, z64* out, int n);
+  void h_block_on(System& s, const HView& w, const z64* in, z64* out, int n, hipStream_t st);
+  // H c without allocating (work space in a static device array), on `stream`
+  void apply_h_noalloc(int id, int nvec, const double* in, double* out, hipStream_t stream);
   void h_scratch(System& s, HScratch& w, int cap);
   Budget* budget() { return &budget_; }
   hipStream_t stream() const { return st_; }
