@@ -60,7 +60,7 @@ class sth_ticket_info(C.Structure):
 class sth_system_info(C.Structure):
     _fields_ = [("npw", C.c_int), ("nsticks", C.c_int), ("nslots", C.c_int), ("nv", C.c_int),
                 ("nproj", C.c_int), ("fft_plan_fp64", C.c_int), ("fft_plan_fp32", C.c_int),
-                ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 32),
+                ("gemm_kchunk", C.c_int), ("tune_ms", C.c_double * 48),
                 ("tuned_from_cache", C.c_int), ("plane_kernel_fp64", C.c_int),
                 ("plane_kernel_fp32", C.c_int), ("zfft_kernel_fp64", C.c_int),
                 ("zfft_kernel_fp32", C.c_int), ("n", C.c_int), ("budget_used", C.c_size_t),

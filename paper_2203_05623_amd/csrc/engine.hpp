@@ -171,7 +171,7 @@ struct System {
 
   // hipGraph of `graph_nit` CG iterations over every slot (steady state), one per
   // operator precision; captured on first use, replayed each check period
-  double tune_ms[32] = {};         // autotuner timings (see sth_system_info)
+  double tune_ms[48] = {};         // autotuner timings (see sth_system_info)
   int tuned_from_cache = 0;
   DevMem d_ident;                  // [nslots] 0..nslots-1
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};

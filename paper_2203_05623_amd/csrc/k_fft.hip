@@ -230,6 +230,8 @@ __device__ inline void pass_twiddles(const cpx<T>* tw, int j, cpx<T>* w) {
 struct RowBits {
   unsigned long long lo, hi;
   __device__ RowBits(const GridDev& g, int i1) : lo(g.rowbits[2 * i1]), hi(g.rowbits[2 * i1 + 1]) {}
+  __device__ RowBits(const unsigned long long* bits, int i1)
+      : lo(bits[2 * i1]), hi(bits[2 * i1 + 1]) {}
   __device__ bool operator()(int i2) const {
     return ((i2 < 64 ? lo >> i2 : hi >> (i2 - 64)) & 1ull) != 0;
   }
@@ -290,9 +292,16 @@ constexpr size_t fused_lds_bytes() {
   return size_t(N) * fused_pitch<N, T>() * sizeof(cpx<T>);
 }
 
-template <int N, int P, typename T>
-__global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
-    GridDev g, VecSet<cpx<T>> sticks, const int* slots, const T* pot, const T* const* pot_ptr) {
+// The passes A1 .. A1h on the tile (stick cells already in place).  The
+// plane-independent tables come in as pointers (global memory, or an LDS copy):
+// rows = the active rows (row_list), bits = their stick bit masks (rowbits),
+// tw = the twiddles.  vget(q, r) gives the potential at the r-th point of this
+// thread's q-th B2 butterfly; after_b2() runs once the last of those values
+// has been read.
+template <int N, int P, typename T, typename VGet, typename AfterB2>
+__device__ inline void fused_passes(cpx<T>* tile, const GridDev& g, const int* rows,
+                                    const unsigned long long* bits, const cpx<T>* tw,
+                                    VGet vget, AfterB2 after_b2) {
   constexpr int NT = fused_threads<N, P>();
   constexpr int NP = fused_pitch<N, T>();
   constexpr int R1 = RadixPlan<N, P>::radix(0), R2 = RadixPlan<N, P>::radix(1);
@@ -300,17 +309,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
   constexpr int M1 = N / R1, M2 = N / R2;
   constexpr int TB1 = (N * M1 + NT - 1) / NT;
   constexpr int TB2 = (N * M2 + NT - 1) / NT;
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int slot = slots[blockIdx.y];
-  const int i0 = blockIdx.x;
-  cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
-  const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
-  const cpx<T>* tw = twiddles<T>(g);
   const int nrow = g.nrow;
-
-  sticks_to_tile<N, NT, T, NP>(tile, g, row);
-  __syncthreads();
   {   // A1: loads, barrier, stores (in place along the row)
     constexpr int TA = (N / 2 * M1 + NT - 1) / NT;   // at most N/2 active rows
     cpx<T> v[TA][R1];
@@ -319,8 +318,8 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       const int t = threadIdx.x + q * NT;
       if (t < nrow * M1) {
         const int f = t / M1, j = t - f * M1;
-        const int i1 = g.row_list[f];
-        const RowBits has(g, i1);
+        const int i1 = rows[f];
+        const RowBits has(bits, i1);
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
           v[q][r] = cpx<T>{T(0), T(0)};
@@ -334,7 +333,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       const int t = threadIdx.x + q * NT;
       if (t < nrow * M1) {
         const int f = t / M1, j = t - f * M1;
-        const int i1 = g.row_list[f];
+        const int i1 = rows[f];
         Dft<R1, +1, T>::run(v[q]);
 #pragma unroll
         for (int p = 0; p < R1; ++p) tile[i1 * NP + j * R1 + p] = v[q][p];
@@ -344,7 +343,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
   __syncthreads();
   for (int t = threadIdx.x; t < nrow * M2; t += NT) {   // A2
     const int j = t / nrow, f = t - j * nrow;
-    const int i1 = g.row_list[f];
+    const int i1 = rows[f];
     cpx<T> v[R2], w[R2];
     pass_twiddles<R2>(tw, j, w);
 #pragma unroll
@@ -397,13 +396,14 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       for (int r = 1; r < R2; ++r) v[r] = v[r] * conj(w[r]);
       Dft<R2, +1, T>::run(v);
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[r] = scale(v[r], V[(j + r * M2) * N + c]);
+      for (int r = 0; r < R2; ++r) v[r] = scale(v[r], vget(q, r));
       Dft<R2, -1, T>::run(v);
       tile[j * NP + c] = v[0];
 #pragma unroll
       for (int r = 1; r < R2; ++r) tile[(j + r * M2) * NP + c] = v[r] * w[r];
     }
   }
+  after_b2();
   __syncthreads();
   {   // B1h
     cpx<T> v[TB1][R1];
@@ -434,7 +434,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
   __syncthreads();
   for (int t = threadIdx.x; t < nrow * M2; t += NT) {   // A2h
     const int j = t / nrow, f = t - j * nrow;
-    const int i1 = g.row_list[f];
+    const int i1 = rows[f];
     cpx<T> v[R2], w[R2];
     pass_twiddles<R2>(tw, j, w);
 #pragma unroll
@@ -454,7 +454,7 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       const int t = threadIdx.x + q * NT;
       if (t < nrow * M1) {
         const int f = t / M1, j = t - f * M1;
-        const int i1 = g.row_list[f];
+        const int i1 = rows[f];
 #pragma unroll
         for (int p = 0; p < R1; ++p) v[q][p] = tile[i1 * NP + j * R1 + p];
       }
@@ -465,15 +465,170 @@ __global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
       const int t = threadIdx.x + q * NT;
       if (t < nrow * M1) {
         const int f = t / M1, j = t - f * M1;
-        const int i1 = g.row_list[f];
+        const int i1 = rows[f];
         Dft<R1, -1, T>::run(v[q]);
 #pragma unroll
         for (int r = 0; r < R1; ++r) tile[i1 * NP + j + r * M1] = v[q][r];
       }
     }
   }
+}
+
+// Position in the B2 butterfly layout of this thread's q-th butterfly, point r:
+// index of V[i1][i2] in the plane, or -1 past the end.
+template <int N, int P>
+__device__ inline int b2_index(int q, int r) {
+  constexpr int NT = fused_threads<N, P>();
+  constexpr int R2 = RadixPlan<N, P>::radix(1), M2 = N / R2;
+  const int t = threadIdx.x + q * NT;
+  if (t >= N * M2) return -1;
+  const int j = t / N, c = t - j * N;
+  return (j + r * M2) * N + c;
+}
+
+template <int N, int P, typename T>
+__global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused(
+    GridDev g, VecSet<cpx<T>> sticks, const int* slots, const T* pot, const T* const* pot_ptr) {
+  constexpr int NT = fused_threads<N, P>();
+  constexpr int NP = fused_pitch<N, T>();
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int slot = slots[blockIdx.y];
+  const int i0 = blockIdx.x;
+  cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+  const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+  sticks_to_tile<N, NT, T, NP>(tile, g, row);
+  __syncthreads();
+  fused_passes<N, P, T>(tile, g, g.row_list, g.rowbits, twiddles<T>(g),
+                        [V](int q, int r) { return V[b2_index<N, P>(q, r)]; }, [] {});
   __syncthreads();
   tile_to_sticks<N, NT, T, NP>(tile, g, row);
+}
+
+// Global-address-space view of a pointer that came out of memory (a load
+// through a generic pointer would be a flat load, which the barrier's LDS wait
+// also waits for).
+template <typename T>
+__device__ inline T ld_global(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)   // the host pass of this device function has no address spaces
+  return *(const __attribute__((address_space(1))) T*)(p);
+#else
+  return *p;
+#endif
+}
+
+// Address of plane q (column q / N, plane q % N) of k_plane_fused_pf: its
+// stick row and its potential plane.
+template <int N, typename T>
+__device__ inline void pf_plane_ptrs(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots,
+                                     const T* pot, const T* const* pot_ptr, long long q,
+                                     cpx<T>*& row, const T*& V) {
+  const int c = int(q / N), i0 = int(q - (long long)c * N);
+  const int slot = slots[c];
+  row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+  V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+}
+
+// Persistent form of k_plane_fused (plane kind 3): one workgroup per CU walks
+// the planes of every column with a stride of the grid size.  The single-pass
+// tile fills the LDS, so the plain form has one workgroup per CU and nothing to
+// hide its load latency behind; here each plane's global loads are issued one
+// plane ahead into registers: the next plane's stick values as soon as the
+// current ones are in the tile, its potential values as soon as the current
+// B2 pass has read its own.  The loads are unconditional (lanes without a
+// stick or a butterfly read element 0), so the values stay in registers.
+template <int N, int P>
+constexpr int pf_sticks_per_thread() {   // an alias-free sphere has < N^2 / 4 sticks
+  return (N * N / 4 + fused_threads<N, P>() - 1) / fused_threads<N, P>();
+}
+// LDS of k_plane_fused_pf: the tile, then copies of the twiddles (N), the
+// row bit masks (2 N words) and the active-row list (N / 2 entries).
+template <int N, typename T>
+constexpr size_t pf_lds_bytes() {
+  return fused_lds_bytes<N, T>() + size_t(N) * sizeof(cpx<T>) + size_t(2 * N) * 8 +
+         size_t(N / 2) * 4;
+}
+template <int N, int P, typename T>
+__global__ __launch_bounds__((fused_threads<N, P>())) void k_plane_fused_pf(
+    GridDev g, VecSet<cpx<T>> sticks, const int* __restrict__ slots, int ncols,
+    const T* pot, const T* const* __restrict__ pot_ptr) {
+  constexpr int NT = fused_threads<N, P>();
+  constexpr int NP = fused_pitch<N, T>();
+  constexpr int R2 = RadixPlan<N, P>::radix(1), M2 = N / R2;
+  constexpr int TB2 = (N * M2 + NT - 1) / NT;
+  constexpr int SPT = pf_sticks_per_thread<N, P>();
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem_raw);
+  // plane-independent tables in LDS, so that the passes issue no global load
+  // (a wait for one would also wait for every prefetch issued before it)
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw + fused_lds_bytes<N, T>());
+  unsigned long long* bits = reinterpret_cast<unsigned long long*>(tw + N);
+  int* rows = reinterpret_cast<int*>(bits + 2 * N);
+  {
+    const cpx<T>* gtw = twiddles<T>(g);
+    for (int i = threadIdx.x; i < N; i += NT) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < 2 * N; i += NT) bits[i] = g.rowbits[i];
+    for (int i = threadIdx.x; i < g.nrow; i += NT) rows[i] = g.row_list[i];
+  }
+  // tile cell of this thread's sticks (the same for every plane); lanes past
+  // the last stick take the padding cell (0, N), which no pass reads
+  int pos[SPT];
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int s = threadIdx.x + k * NT;
+    pos[k] = N;
+    if (s < g.nst) {
+      const int p = g.stick_i12[s];
+      const int i1 = p / N;
+      pos[k] = i1 * NP + (p - i1 * N);
+    }
+  }
+  cpx<T> sv[SPT];
+  T vv[TB2][R2];
+  auto load_sticks = [&](const cpx<T>* row) {
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      sv[k] = ld_global(row + (pos[k] != N ? threadIdx.x + k * NT : 0));
+  };
+  auto load_pot = [&](const T* V) {
+#pragma unroll
+    for (int q2 = 0; q2 < TB2; ++q2)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int e = b2_index<N, P>(q2, r);
+        vv[q2][r] = ld_global(V + (e >= 0 ? e : 0));
+      }
+  };
+  const long long nplanes = (long long)ncols * N, step = gridDim.x;
+  long long q = blockIdx.x;
+  if (q >= nplanes) return;
+  cpx<T>* row;
+  const T* V;
+  pf_plane_ptrs<N, T>(g, sticks, slots, pot, pot_ptr, q, row, V);
+  load_sticks(row);
+  load_pot(V);
+  // The loads are issued without branches (after the last plane they fetch
+  // that plane again, and the values go unused), so that every wait for them
+  // is a partial one.
+  for (; q < nplanes; q += step) {
+    cpx<T>* nrow = row;
+    const T* nV = V;
+    if (q + step < nplanes)
+      pf_plane_ptrs<N, T>(g, sticks, slots, pot, pot_ptr, q + step, nrow, nV);
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) tile[pos[k]] = sv[k];
+    load_sticks(nrow);
+    __syncthreads();
+    fused_passes<N, P, T>(tile, g, rows, bits, tw, [&vv](int q2, int r) { return vv[q2][r]; },
+                          [&] { load_pot(nV); });
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      if (pos[k] != N) row[threadIdx.x + k * NT] = tile[pos[k]];
+    __syncthreads();   // the next plane's sticks overwrite the tile
+    row = nrow;
+    V = nV;
+  }
 }
 
 // H_loc on one plane, wave form: the passes of k_plane_fused, with every
@@ -1234,8 +1389,21 @@ void launch_zfft_inv(const GridDev& g, VecSet<const Tin> in, VecSet<cpx<T>> stic
   STH_HIP_CHECK(hipGetLastError());
 }
 
+// Compute units of the current device (the persistent plane form sizes its
+// grid by them).
+inline int device_cus() {
+  static const int n = [] {
+    int dev = 0, v = 0;
+    STH_HIP_CHECK(hipGetDevice(&dev));
+    STH_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+    return v > 0 ? v : 1;
+  }();
+  return n;
+}
+
 // Plane kernel variants (GridDev::plane_kind): 0 single-pass workgroup form,
-// 1 wave form, 2 strip form (the only one for grids above kTileMaxN).
+// 1 wave form, 2 strip form (the only one for grids above kTileMaxN),
+// 3 persistent single-pass form with the next plane's loads in flight.
 template <typename T>
 void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
                         const T* pot, const T* const* pot_ptr, hipStream_t st) {
@@ -1264,6 +1432,24 @@ void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slot
       constexpr int nt = fused_threads<NN, PP>();
       hipLaunchKernelGGL((k_plane_fused<NN, PP, T>), grid, dim3(nt), sm, st, g, sticks, slots,
                          pot, pot_ptr);
+    } else if (kind == kPlanePersistent) {
+      constexpr size_t sm = pf_lds_bytes<NN, T>();
+      constexpr int nt = fused_threads<NN, PP>();
+      if (g.nst > pf_sticks_per_thread<NN, PP>() * nt) {
+        set_error("persistent plane kernel: %d sticks exceed %d", g.nst,
+                  pf_sticks_per_thread<NN, PP>() * nt);
+        throw Error(STH_E_INVALID);
+      }
+      static const int per_cu = [] {
+        int b = 0;
+        STH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &b, reinterpret_cast<const void*>(&k_plane_fused_pf<NN, PP, T>), nt, sm));
+        return b > 0 ? b : 1;
+      }();
+      const long long np = (long long)ncols * NN;
+      const dim3 pg((unsigned)std::min<long long>(np, (long long)per_cu * device_cus()));
+      hipLaunchKernelGGL((k_plane_fused_pf<NN, PP, T>), pg, dim3(nt), sm, st, g, sticks, slots,
+                         ncols, pot, pot_ptr);
     } else {
       using S = PlaneWave<NN, PP>;
       constexpr size_t sm = S::lds_bytes(sizeof(cpx<T>));
@@ -1363,6 +1549,8 @@ void prepare_fft_kernels(int N) {
     STH_DISPATCH_NP(N, p, {
       set_smem<k_plane_fused<NN, PP, double>>(fused_lds_bytes<NN, double>());
       set_smem<k_plane_fused<NN, PP, float>>(fused_lds_bytes<NN, float>());
+      set_smem<k_plane_fused_pf<NN, PP, double>>(pf_lds_bytes<NN, double>());
+      set_smem<k_plane_fused_pf<NN, PP, float>>(pf_lds_bytes<NN, float>());
       set_smem<k_plane_wave<NN, PP, double>>(PlaneWave<NN, PP>::lds_bytes(sizeof(z64)));
       set_smem<k_plane_wave<NN, PP, float>>(PlaneWave<NN, PP>::lds_bytes(sizeof(z32)));
       set_smem<k_plane_to_grid<NN, PP, double>>(PlaneLds<NN, double>::bytes(false));

@@ -67,9 +67,10 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // LDS attributes of the plane kernels of grid N (call before any graph capture)
 void prepare_fft_kernels(int N);
 constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
-constexpr int kPlaneKinds = 3;       // plane kernels: workgroup form, wave form, strip form
+constexpr int kPlaneKinds = 4;       // plane kernels: workgroup, wave, strip, persistent forms
 constexpr int kZfftKinds = 2;        // z-stick kernels: workgroup form, wave form
 constexpr int kPlaneStrips = 2;      // plane_kind of the strip form
+constexpr int kPlanePersistent = 3;  // plane_kind of the persistent single-pass form
 constexpr int kTileMaxN = 96;        // largest grid whose N x (N + 1) FP64 plane tile fits in LDS
 constexpr int kStageSlots = 1024;    // strip-form persistent workgroups (up to four per CU)
 

@@ -122,11 +122,12 @@ void Context::autotune(System& s) {
   // form), per precision; grids whose plane tile exceeds the LDS have the strip
   // form only
   const int kind0 = s.N > kTileMaxN ? kPlaneStrips : 0;
+  const int kind1 = s.N > kTileMaxN ? kPlaneStrips + 1 : kPlaneKinds;
   for (int k = 0; k < 2; ++k) {
     double bt = 1e300;
     int bp = 0, bkind = kind0, bz = 0;
     for (int zk = 0; zk < kZfftKinds; ++zk) {
-      for (int kind = kind0; kind < kPlaneKinds; ++kind) {
+      for (int kind = kind0; kind < kind1; ++kind) {
         for (int p = 0; p < kRadixPlansHost; ++p) {
           s.g.plan[k] = p;
           s.g.plane_kind[k] = kind;
@@ -144,7 +145,7 @@ void Context::autotune(System& s) {
                                           ZF_PLAIN, {nullptr, 0}, nullptr, st_);
             }
           });
-          s.tune_ms[12 * k + 6 * zk + 2 * kind + p] = ms;
+          s.tune_ms[16 * k + 8 * zk + 2 * kind + p] = ms;
           if (ms < bt) {
             bt = ms;
             bp = p;
@@ -173,7 +174,7 @@ void Context::autotune(System& s) {
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[24 + ncand++] = ms;
+    s.tune_ms[32 + ncand++] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;
@@ -207,7 +208,7 @@ void Context::system_info(int id, sth_system_info* info) {
   info->zfft_kernel_fp64 = s.g.zfft_kind[0];
   info->zfft_kernel_fp32 = s.g.zfft_kind[1];
   info->gemm_kchunk = s.kchunk;
-  for (int i = 0; i < 32; ++i) info->tune_ms[i] = s.tune_ms[i];
+  for (int i = 0; i < 48; ++i) info->tune_ms[i] = s.tune_ms[i];
   info->tuned_from_cache = s.tuned_from_cache;
   info->n = s.N;
   info->budget_used = budget_.used();

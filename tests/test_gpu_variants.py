@@ -2,8 +2,8 @@
 
 The autotuner keeps the fastest (radix plan, plane kernel form, z-stick kernel
 form) per precision, so a normal run exercises only one of them.  Here every radix
-plan and every kernel form of both stages (plane: workgroup, wave and strip
-forms; z-sticks: workgroup and wave forms) is forced through the tuning cache
+plan and every kernel form of both stages (plane: workgroup, wave, strip and
+persistent forms; z-sticks: workgroup and wave forms) is forced through the tuning cache
 (STH_TUNE_CACHE) in FP64 and in FP32 and checked against the oracle: H.psi in FP64
 (1e-12 relative) and mixed-precision solves, whose inner operator uses the FP32
 variant (1e-6 relative on Delta psi at true residual 1e-8).  On config 1 also FP64
@@ -23,7 +23,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
-VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1, 2)]
+VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1, 2, 3)]
 
 
 def _force(path, info, M, plan, kind):
