@@ -36,12 +36,16 @@ MI355X_HBM_GBS = 8000.0
 MI355X_FP64_TFLOPS = 78.6     # FP64 vector ALU and FP64 dense MFMA
 MI355X_FP32_TFLOPS = 157.3    # FP32 vector ALU and FP32 dense MFMA
 MI355X_BF16_TFLOPS = 2500.0   # BF16 dense MFMA
-# (phase, precision) -> measured HBM bytes / algorithmic bytes of its kernel
-# (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, see profiles/); entries are dropped
-# whenever the kernel changes
-HBM_OVER_ALGORITHMIC = {("plane", "fp64"): 1.0045,
-                        # both mixed forms run the same plane kernels
-                        ("plane", "mixed"): 1.0088, ("plane", "mixed-bf16"): 1.0088}
+# (workload, phase, precision) -> measured HBM bytes / algorithmic bytes of the
+# phase's kernels over one run of the same workload (rocprofv3 FETCH_SIZE x2 +
+# WRITE_SIZE, summed over every launch of the phase; profiles/ holds the
+# summaries and commands); entries are dropped whenever those kernels change
+HBM_OVER_ALGORITHMIC = {
+    # 144^3: split-K projector GEMM (W and P tiles re-read per row / column tile)
+    ("cfg5", "gemm_ah_b", "fp64"): 4.744,
+    # 144^3 strip-form plane kernels (scratch plane Y in HBM between directions)
+    ("cfg5", "plane", "fp64"): 7.421, ("cfg5", "plane", "mixed-bf16"): 6.536,
+}
 # --precision: FP64 solves; mixed (FP32 inner operator, FP32-MFMA projector
 # GEMMs); mixed-bf16 (FP32 inner operator, BF16-MFMA hi/lo projector GEMMs)
 PRECISIONS = {"fp64": lambda P: P.STH_FP64, "mixed": lambda P: P.STH_MIXED,
@@ -369,7 +373,7 @@ def _peak(kind, precision, nproj, nv):
     return MI355X_FP32_TFLOPS
 
 
-def _roofline(prof, precision, nproj, nv):
+def _roofline(prof, precision, nproj, nv, workload):
     dom = max(prof, key=lambda k: prof[k][0])
     ms, nl, by, fl = prof[dom]
     kind = {"gemm_ah_b": "mfma", "gemm_a_c": "mfma", "plane": "alu"}.get(dom, "hbm")
@@ -382,7 +386,7 @@ def _roofline(prof, precision, nproj, nv):
         if kind == "mfma" and precision == "mixed-bf16":
             roof["peak_blend"] = {"bf16_x3_rows": int(nproj), "fp32_rows": int(nv)}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    ratio = HBM_OVER_ALGORITHMIC.get((dom, precision))
+    ratio = HBM_OVER_ALGORITHMIC.get((workload, dom, precision))
     roof["traffic"] = None if ratio is None else ratio * by / max(nl, 1)
     roof["traffic_unit"] = "bytes/launch"
     roof["kernel"] = dom
@@ -476,7 +480,7 @@ def run_workload(P, torch, name, npert, args, pool=None):
             torch.cuda.synchronize()
             prof = P.sth_profile_read(ctx)
             P.sth_profile(ctx, False)
-            roof = _roofline(prof, args.precision, beta.shape[0], cfg.nv)
+            roof = _roofline(prof, args.precision, beta.shape[0], cfg.nv, name)
             phases = {k: {"ms": round(v[0], 3), "launches": v[1],
                           "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
                           "TFLOP/s": (round(v[3] / (v[0] * 1e-3) / 1e12, 2)
