@@ -153,8 +153,8 @@ typedef struct {
   int fft_plan_fp64, fft_plan_fp32;   /* 0 or 1: index of the radix factorisation */
   int gemm_kchunk;                    /* split-K chunk of C = W^H P */
   double tune_ms[48];                 /* timings behind the choice, ms per launch set:
-                                         [16 p + 8 zkind + 2 kind + plan] for precision p
-                                         (0 FP64, 1 FP32), 0 where not timed; [32 + i]
+                                         [20 p + 10 zkind + 2 kind + plan] for precision p
+                                         (0 FP64, 1 FP32), 0 where not timed; [40 + i]
                                          split-K candidate i < 8 (32, 24, 16, 12, 11, 8,
                                          6, 4 chunks, repeats skipped) */
   int tuned_from_cache;
@@ -162,12 +162,16 @@ typedef struct {
                                                  form, 1 wave form (every row / column
                                                  owned by one wavefront), 2 strip form
                                                  (the plane in strips of rows and columns
-                                                 through a scratch plane; the only form
-                                                 of grids above 96, whose plane tile
-                                                 exceeds the LDS), 3 persistent
+                                                 through a scratch plane; with 4 the only
+                                                 forms of grids above 96, whose plane
+                                                 tile exceeds the LDS), 3 persistent
                                                  single-pass form (one workgroup per CU
                                                  walks the planes, loading the next
-                                                 plane while transforming one) */
+                                                 plane while transforming one), 4
+                                                 compact-row form (only the active rows
+                                                 in LDS, every transform in the
+                                                 registers of 8 or 16 lanes; any grid
+                                                 whose active rows fit the LDS) */
   int zfft_kernel_fp64, zfft_kernel_fp32;     /* z-stick kernel form ("zkind"): 0
                                                  workgroup form, 1 wave form */
   int n;                              /* FFT grid points per axis */

@@ -343,6 +343,23 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
       }
     s.d_rowbits = upload(&budget_, bits, st_);
   }
+  {
+    // stick range of each active row (the sticks are sorted by (m1, m2), so the
+    // sticks of one i1 row are contiguous): read by the compact-row form
+    std::vector<int> fof(N, -1);
+    for (int f = 0; f < s.nrow; ++f) fof[sb.row_list[f]] = f;
+    std::vector<int> range((size_t)2 * s.nrow, -1);
+    for (int k = 0; k < s.nst; ++k) {
+      const int f = fof[sb.stick_i12[k] / N];
+      if (range[2 * f] < 0) range[2 * f] = k;
+      if (range[2 * f + 1] >= 0 && range[2 * f + 1] != k) {
+        set_error("internal: sticks of row %d are not contiguous", sb.row_list[f]);
+        throw Error(STH_E_INTERNAL);
+      }
+      range[2 * f + 1] = k + 1;
+    }
+    s.d_row_srange = upload(&budget_, range, st_);
+  }
   s.d_kin = upload(&budget_, sb.kin, st_);
   s.d_perm = upload(&budget_, sb.perm, st_);
   std::vector<z64> tw64(N);
@@ -363,6 +380,7 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.g.stick_i12 = s.d_stick_i12.as<int>();
   s.g.row_list = s.d_row_list.as<int>();
   s.g.rowbits = s.d_rowbits.as<unsigned long long>();
+  s.g.row_srange = s.d_row_srange.as<int>();
   for (int r : sb.row_list) s.g.rowmask[r >> 6] |= 1ull << (r & 63);
   s.g.kin = s.d_kin.as<double>();
   s.g.tw64 = s.d_tw64.as<z64>();

@@ -142,7 +142,8 @@ struct System {
   int m2 = 0;          // largest |m|^2 on the sphere (density sphere: |m|^2 <= 4 m2)
   double L = 0.0, omega = 0.0, fs = 2.0;
   GridDev g;
-  DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_kin, d_tw64, d_tw32, d_perm;
+  DevMem d_stick_off, d_elem_pos, d_stick_i12, d_row_list, d_rowbits, d_row_srange, d_kin, d_tw64,
+      d_tw32, d_perm;
   DevMem d_stage;      // [kStageSlots][nrow][N] z64 scratch planes of the strip-form kernels
   DevMem d_W;          // [nv + nproj][npw] z64, internal order: psi_v rows, then beta rows
   DevMem d_diag;       // [nv + nproj]: 0 on psi_v rows, D_p on beta rows

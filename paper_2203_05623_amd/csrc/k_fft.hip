@@ -21,6 +21,9 @@
 // pass is one round of work between two barriers.
 #include <algorithm>
 
+#include <map>
+#include <mutex>
+
 #include "errors.hpp"
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -1221,6 +1224,233 @@ __global__ __launch_bounds__((Strips<N, T>::NT)) void k_plane_strips(
   }
 }
 
+// ------------------------------------------------------------------ compact-row planes
+// Plane form that keeps only the active rows of a plane, Y[f][i2] for the nrow
+// rows f of row_list, in LDS (nrow x N complex, no padding: 71 x 144 FP64 is
+// 163,584 B), so that no scratch plane goes through HBM.  Every length-N
+// transform runs in the registers of a group of L lanes (N = L R): lane l holds
+// the elements l + L r (r < R), takes the radix-R DFT over r in its registers,
+// the twiddles w_N^(l p), and a radix-2 network of log2 L stages across the
+// lanes of its group (DPP lane selects, no LDS).  LDS is only the exchange between the
+// row transforms (along i2) and the column transforms (along i1).
+//
+// Index algebra (n = l + L r, k = p + R q): X[p + R q] =
+//   sum_l w_L^(l q) w_N^(l p) sum_r x[l + L r] w_R^(r p);
+// the lane network is decimation in frequency (natural order in, lane
+// bitrev(q) holding q out) for the inverse transform, and its adjoint,
+// decimation in time (bit-reversed in, natural out), for the forward one.
+//
+// LDS rows are rotated by their index (element c of row f at f N + (c + f) mod N),
+// so that the L lanes of a column transform, which read L consecutive rows of
+// one column, hit distinct banks.
+template <int N>
+struct RowsForm {
+  static constexpr int L = (N % 16 == 0) ? 16 : 8;   // lanes per transform
+  static constexpr int R = N / L;                      // elements per lane
+  static constexpr int LOG2L = L == 16 ? 4 : 3;
+  // groups of L lanes per workgroup, so that the N columns split evenly
+  static constexpr int G = N == 144 ? 36 : (N == 96 ? 48 : (N == 72 ? 72 : (N == 48 ? 48 : 24)));
+  static constexpr int NT = G * L;
+  static_assert(NT % 64 == 0 && NT <= 1024, "workgroup shape");
+  static_assert(R == 3 || R == 6 || R == 9, "in-lane radix");
+};
+
+// LDS bytes of the compact-row form for a grid with nrow active rows
+template <int N, typename T>
+inline size_t rows_lds_bytes(int nrow) {
+  return size_t(nrow) * N * sizeof(cpx<T>);
+}
+
+// Position of row i1 in the (ascending) active-row list, -1 for an empty row:
+// a popcount of the row mask below i1 (N <= 192), so that no table takes LDS.
+__device__ inline int compact_row(const GridDev& g, int i1) {
+  const int w = i1 >> 6, b = i1 & 63;
+  const unsigned long long mw = w == 0 ? g.rowmask[0] : (w == 1 ? g.rowmask[1] : g.rowmask[2]);
+  if (((mw >> b) & 1ull) == 0) return -1;
+  int f = __popcll(mw & ((1ull << b) - 1ull));
+  if (w >= 1) f += __popcll(g.rowmask[0]);
+  if (w >= 2) f += __popcll(g.rowmask[1]);
+  return f;
+}
+
+template <int N>
+__device__ inline int rows_rot(int f, int c) {
+  const int x = c + f;
+  return x >= N ? x - N : x;
+}
+
+// Value of lane l ^ m (m = 1, 2, 4, 8) through DPP lane selects in the vector
+// ALU instead of the LDS crossbar: xor 1 and xor 2 are quad permutations, xor 8
+// is a rotation by 8 of a 16-lane row, xor 4 reverses each quad and then each
+// half-row (i -> i ^ 3 -> i ^ 3 ^ 7).
+template <int CTRL>
+__device__ inline int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp_sel(float v) {
+  return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ inline double dpp_sel(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = unsigned(dpp32<CTRL>(int(unsigned(b))));
+  const unsigned hi = unsigned(dpp32<CTRL>(int(unsigned(b >> 32))));
+  return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+template <typename T>
+__device__ inline T lane_xor1(T v, int m) {
+  constexpr int kQuadSwap1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+  constexpr int kQuadSwap2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+  constexpr int kQuadReverse = 0x1B;    // quad_perm [3, 2, 1, 0]
+  constexpr int kRowHalfMirror = 0x141;
+  constexpr int kRowRor8 = 0x128;
+  switch (m) {
+    case 1: return dpp_sel<kQuadSwap1>(v);
+    case 2: return dpp_sel<kQuadSwap2>(v);
+    case 4: return dpp_sel<kRowHalfMirror>(dpp_sel<kQuadReverse>(v));
+    default: return dpp_sel<kRowRor8>(v);
+  }
+}
+template <typename T>
+__device__ inline cpx<T> lane_xor(cpx<T> v, int m) {
+  return cpx<T>{lane_xor1(v.x, m), lane_xor1(v.y, m)};
+}
+
+// Length-N transform held by a lane group.  inverse(): natural element order
+// (lane l, register r = element l + L r) to lane l, register p = element
+// p + R bitrev(l).  forward(): the adjoint, that layout back to natural order.
+// tw: the table exp(-2 pi i t / N).
+template <int N, typename T>
+struct LaneFFT {
+  using F = RowsForm<N>;
+  static constexpr int L = F::L, R = F::R;
+  __device__ static int bitrev(int l) {
+    return int(__builtin_bitreverse32(unsigned(l)) >> (32 - F::LOG2L));
+  }
+  __device__ static void inverse(cpx<T> (&v)[R], const cpx<T>* tw, int l) {
+    Dft<R, +1, T>::run(v);
+    cpx<T> w[R];
+    pass_twiddles<R>(tw, l, w);   // w[p] = w_N^(-l p); the inverse takes the conjugates
+#pragma unroll
+    for (int p = 1; p < R; ++p) v[p] = v[p] * conj(w[p]);
+#pragma unroll
+    for (int h = L / 2; h >= 1; h >>= 1) {   // decimation in frequency, sign +
+      const bool bottom = (l & h) != 0;
+      const cpx<T> wt = conj(tw[(l & (h - 1)) * (N / (2 * h))]);
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        const cpx<T> u = lane_xor(v[p], h);
+        v[p] = bottom ? (u - v[p]) * wt : v[p] + u;
+      }
+    }
+  }
+  __device__ static void forward(cpx<T> (&v)[R], const cpx<T>* tw, int l) {
+#pragma unroll
+    for (int h = 1; h < L; h <<= 1) {   // decimation in time, sign -
+      const bool bottom = (l & h) != 0;
+      const cpx<T> wt = tw[(l & (h - 1)) * (N / (2 * h))];
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        const cpx<T> u = lane_xor(v[p], h);
+        v[p] = bottom ? u - v[p] * wt : v[p] + u * wt;
+      }
+    }
+    cpx<T> w[R];
+    pass_twiddles<R>(tw, l, w);
+#pragma unroll
+    for (int p = 1; p < R; ++p) v[p] = v[p] * w[p];
+    Dft<R, -1, T>::run(v);
+  }
+};
+
+// H_loc (or Delta V_j) on every plane of ncols vectors, compact-row form
+// (plane kind 4).  Persistent grid: one workgroup per CU walks the planes.
+// Per plane: (A) each lane group takes rows f (f = group, group + G, ...):
+// clears its row, scatters the row's sticks into it (the sticks of one row are
+// a contiguous range), inverse transform along i2, back to the row; (B) each
+// group takes columns: gathers the active rows of the column, inverse along
+// i1, multiplies by V, forward along i1, writes the active rows back; (C)
+// the row groups again: forward along i2, stick cells back to the stick row.
+// A group touches only its own rows in (A) and (C), so the LDS writes and
+// reads of one row stay inside one wavefront (in order); two workgroup
+// barriers per plane separate (A), (B) and (C).
+template <int N, typename T>
+__global__ __launch_bounds__((RowsForm<N>::NT)) void k_plane_rows(
+    GridDev g, VecSet<cpx<T>> sticks, const int* __restrict__ slots, int ncols, const T* pot,
+    const T* const* __restrict__ pot_ptr) {
+  using F = RowsForm<N>;
+  using X = LaneFFT<N, T>;
+  constexpr int L = F::L, R = F::R, G = F::G;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* Y = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int nrow = g.nrow;
+  const int l = threadIdx.x % L, grp = threadIdx.x / L;
+  const int lq = X::bitrev(l);
+  const cpx<T>* tw = twiddles<T>(g);
+  const long long nplanes = (long long)ncols * N;
+  for (long long q = blockIdx.x; q < nplanes; q += gridDim.x) {
+    const int c = int(q / N), i0 = int(q - (long long)c * N);
+    const int slot = slots[c];
+    cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
+    const T* V = (pot_ptr ? pot_ptr[slot] : pot) + (long long)i0 * N * N;
+    // (A) rows, inverse along i2
+    for (int f = grp; f < nrow; f += G) {
+      cpx<T>* yr = Y + f * N;
+#pragma unroll
+      for (int r = 0; r < R; ++r) yr[l + L * r] = cpx<T>{T(0), T(0)};
+      const int s1 = g.row_srange[2 * f + 1];
+      for (int s = g.row_srange[2 * f] + l; s < s1; s += L) {
+        const int i2 = g.stick_i12[s] % N;
+        yr[rows_rot<N>(f, i2)] = row[s];
+      }
+      cpx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = yr[rows_rot<N>(f, l + L * r)];
+      X::inverse(v, tw, l);
+#pragma unroll
+      for (int p = 0; p < R; ++p) yr[rows_rot<N>(f, p + R * lq)] = v[p];
+    }
+    __syncthreads();
+    // (B) columns: inverse along i1, x V, forward along i1
+    for (int cc = grp; cc < N; cc += G) {
+      cpx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int f = compact_row(g, l + L * r);
+        v[r] = f >= 0 ? Y[f * N + rows_rot<N>(f, cc)] : cpx<T>{T(0), T(0)};
+      }
+      X::inverse(v, tw, l);
+#pragma unroll
+      for (int p = 0; p < R; ++p) v[p] = scale(v[p], V[(p + R * lq) * N + cc]);
+      X::forward(v, tw, l);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int f = compact_row(g, l + L * r);
+        if (f >= 0) Y[f * N + rows_rot<N>(f, cc)] = v[r];
+      }
+    }
+    __syncthreads();
+    // (C) rows, forward along i2, stick cells back
+    for (int f = grp; f < nrow; f += G) {
+      cpx<T>* yr = Y + f * N;
+      cpx<T> v[R];
+#pragma unroll
+      for (int p = 0; p < R; ++p) v[p] = yr[rows_rot<N>(f, p + R * lq)];
+      X::forward(v, tw, l);
+#pragma unroll
+      for (int r = 0; r < R; ++r) yr[rows_rot<N>(f, l + L * r)] = v[r];
+      const int s1 = g.row_srange[2 * f + 1];
+      for (int s = g.row_srange[2 * f] + l; s < s1; s += L) {
+        const int i2 = g.stick_i12[s] % N;
+        row[s] = yr[rows_rot<N>(f, i2)];
+      }
+    }
+    // the next plane's (A) writes only rows this group owns; its (B) waits
+    // for every group at the barrier after (A)
+  }
+}
+
 // psi(r) planes of ncols vectors on the full grid
 template <int N, int P, typename T>
 __global__ __launch_bounds__((Strips<N, T>::NT)) void k_plane_to_grid_strips(
@@ -1401,15 +1631,76 @@ inline int device_cus() {
   return n;
 }
 
+// Largest dynamic LDS of one workgroup on the current device.
+inline size_t device_max_lds() {
+  static const size_t n = [] {
+    int dev = 0, v = 0;
+    STH_HIP_CHECK(hipGetDevice(&dev));
+    STH_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    return size_t(v > 0 ? v : 65536);
+  }();
+  return n;
+}
+
+template <int N, typename T>
+void launch_plane_rows(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
+                       const T* pot, const T* const* pot_ptr, hipStream_t st) {
+  const size_t sm = rows_lds_bytes<N, T>(g.nrow);
+  if (sm > device_max_lds() || !g.row_srange) {
+    set_error("compact-row plane kernel: %d rows of %d need %zu B of LDS (%zu available)",
+              g.nrow, N, sm, device_max_lds());
+    throw Error(STH_E_INVALID);
+  }
+  static std::mutex mu;
+  static std::map<size_t, int> per_cu_of;
+  int per_cu;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per_cu_of.find(sm);
+    if (it == per_cu_of.end()) {
+      int b = 0;
+      STH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b, reinterpret_cast<const void*>(&k_plane_rows<N, T>), RowsForm<N>::NT, sm));
+      it = per_cu_of.emplace(sm, b > 0 ? b : 1).first;
+    }
+    per_cu = it->second;
+  }
+  const long long np = (long long)ncols * N;
+  const dim3 pg((unsigned)std::min<long long>(np, (long long)per_cu * device_cus()));
+  hipLaunchKernelGGL((k_plane_rows<N, T>), pg, dim3(RowsForm<N>::NT), sm, st, g, sticks, slots,
+                     ncols, pot, pot_ptr);
+}
+
+bool plane_kind_available(const GridDev& g, int kind, bool fp32) {
+  if (kind < 0 || kind >= kPlaneKinds) return false;
+  if (kind == kPlaneStrips) return true;
+  if (kind == kPlaneRows) {
+    if (!g.row_srange) return false;
+    size_t sm = 0;
+    STH_DISPATCH_ALL(g.N, 0, {
+      sm = fp32 ? rows_lds_bytes<NN, float>(g.nrow) : rows_lds_bytes<NN, double>(g.nrow);
+    });
+    return sm <= device_max_lds();
+  }
+  return g.N <= kTileMaxN;
+}
+
 // Plane kernel variants (GridDev::plane_kind): 0 single-pass workgroup form,
-// 1 wave form, 2 strip form (the only one for grids above kTileMaxN),
-// 3 persistent single-pass form with the next plane's loads in flight.
+// 1 wave form, 2 strip form (the only tile-free form besides 4), 3 persistent
+// single-pass form with the next plane's loads in flight, 4 compact-row form.
 template <typename T>
 void launch_plane_local(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots, int ncols,
                         const T* pot, const T* const* pot_ptr, hipStream_t st) {
   if (ncols <= 0) return;
   dim3 grid(g.N, ncols);
   const int kind = g.plane_kind[sizeof(T) == 4 ? 1 : 0];
+  if (kind == kPlaneRows) {
+    STH_DISPATCH_ALL(g.N, 0, {
+      launch_plane_rows<NN, T>(g, sticks, slots, ncols, pot, pot_ptr, st);
+    });
+    STH_HIP_CHECK(hipGetLastError());
+    return;
+  }
   if (use_strips(g, kind)) {
     check_stage(g);
     STH_DISPATCH_ALL(g.N, plan_of<T>(g), {
@@ -1538,6 +1829,10 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 // Sets the LDS limits of every plane kernel of grid N up front, so that no
 // attribute call happens while a stream is being captured into a graph.
 void prepare_fft_kernels(int N) {
+  STH_DISPATCH_ALL(N, 0, {
+    set_smem<k_plane_rows<NN, double>>(device_max_lds());
+    set_smem<k_plane_rows<NN, float>>(device_max_lds());
+  });
   for (int p = 0; p < kRadixPlans; ++p) {
     STH_DISPATCH_ALL(N, p, {
       set_smem<k_plane_strips<NN, PP, double>>(Strips<NN, double>::lds_bytes);

@@ -19,6 +19,8 @@ struct GridDev {
   const int* row_list = nullptr;   // [nrow] active i1 rows
   const unsigned long long* rowbits = nullptr;  // [N][2] bit i2 set: (i1, i2) holds a stick
                                                 // (filled for N <= 128, the tile forms' grids)
+  const int* row_srange = nullptr; // [nrow][2] first and one-past-last stick of each active
+                                   // row (the sticks of one row are contiguous)
   unsigned long long rowmask[3] = {0, 0, 0};  // bit i1: row i1 is active (N <= 192)
   const double* kin = nullptr;     // [npw] |G|^2 / 2
   const z64* tw64 = nullptr;       // [N] exp(-2 pi i t / N)
@@ -66,11 +68,17 @@ void launch_drho(const GridDev& g, const z64* sticks, long long stick_stride, in
 
 // LDS attributes of the plane kernels of grid N (call before any graph capture)
 void prepare_fft_kernels(int N);
+// Whether plane kernel form `kind` can run on this grid in FP64 (fp32 = false)
+// or FP32: the tile forms need N <= kTileMaxN, the compact-row form its active
+// rows in one workgroup's LDS.
+bool plane_kind_available(const GridDev& g, int kind, bool fp32);
 constexpr int kRadixPlansHost = 2;   // radix plans per FFT length (see fft.hpp)
-constexpr int kPlaneKinds = 4;       // plane kernels: workgroup, wave, strip, persistent forms
+constexpr int kPlaneKinds = 5;       // plane kernels: workgroup, wave, strip, persistent and
+                                     // compact-row forms
 constexpr int kZfftKinds = 2;        // z-stick kernels: workgroup form, wave form
 constexpr int kPlaneStrips = 2;      // plane_kind of the strip form
 constexpr int kPlanePersistent = 3;  // plane_kind of the persistent single-pass form
+constexpr int kPlaneRows = 4;        // plane_kind of the compact-row form
 constexpr int kTileMaxN = 96;        // largest grid whose N x (N + 1) FP64 plane tile fits in LDS
 constexpr int kStageSlots = 1024;    // strip-form persistent workgroups (up to four per CU)
 

@@ -83,7 +83,7 @@ void Context::autotune(System& s) {
     for (int k = 0; k < 2; ++k)
       ok = ok && c.plan[k] >= 0 && c.plan[k] < kRadixPlansHost && c.kind[k] >= 0 &&
            c.kind[k] < kPlaneKinds && c.zkind[k] >= 0 && c.zkind[k] < kZfftKinds &&
-           (s.N <= kTileMaxN || c.kind[k] == kPlaneStrips);
+           plane_kind_available(s.g, c.kind[k], k == 1);
     if (ok) {
       for (int k = 0; k < 2; ++k) {
         s.g.plan[k] = c.plan[k];
@@ -121,13 +121,13 @@ void Context::autotune(System& s) {
   // FFT stages of H psi for every (radix plan, plane kernel form, z-stick kernel
   // form), per precision; grids whose plane tile exceeds the LDS have the strip
   // form only
-  const int kind0 = s.N > kTileMaxN ? kPlaneStrips : 0;
-  const int kind1 = s.N > kTileMaxN ? kPlaneStrips + 1 : kPlaneKinds;
+
   for (int k = 0; k < 2; ++k) {
     double bt = 1e300;
-    int bp = 0, bkind = kind0, bz = 0;
+    int bp = 0, bkind = kPlaneStrips, bz = 0;
     for (int zk = 0; zk < kZfftKinds; ++zk) {
-      for (int kind = kind0; kind < kind1; ++kind) {
+      for (int kind = 0; kind < kPlaneKinds; ++kind) {
+        if (!plane_kind_available(s.g, kind, k == 1)) continue;
         for (int p = 0; p < kRadixPlansHost; ++p) {
           s.g.plan[k] = p;
           s.g.plane_kind[k] = kind;
@@ -145,7 +145,7 @@ void Context::autotune(System& s) {
                                           ZF_PLAIN, {nullptr, 0}, nullptr, st_);
             }
           });
-          s.tune_ms[16 * k + 8 * zk + 2 * kind + p] = ms;
+          s.tune_ms[20 * k + 10 * zk + 2 * kind + p] = ms;
           if (ms < bt) {
             bt = ms;
             bp = p;
@@ -174,7 +174,7 @@ void Context::autotune(System& s) {
       launch_reduce_parts(s.d_part.as<z64>(), (s.npw + kci - 1) / kci, n, s.M,
                           s.d_diag.as<double>(), 1.0, s.d_C.as<z64>(), st_);
     });
-    s.tune_ms[32 + ncand++] = ms;
+    s.tune_ms[40 + ncand++] = ms;
     if (ms < bt) {
       bt = ms;
       bk = kci;

@@ -2,13 +2,16 @@
 
 96^3 (216 atoms, 54,435 plane waves, 864 KB projectors): the plane tile still
 fits in LDS.  144^3 (512 atoms, 187,511 plane waves, 2048 KB projectors): the
-FP64 plane tile (334 KB) exceeds the LDS, so only the strip form of the plane
-kernels runs there.  Calls go through the C-ABI.
+FP64 plane tile (334 KB) exceeds the LDS, so only the strip form and the
+compact-row form (the 71 active rows, 163,584 B in FP64) of the plane kernels
+run there.  Each test runs with both forms forced through the tuning cache.
+Calls go through the C-ABI.
 
 * H.psi against the oracle's FFT route, 1e-12 relative, on both grids.
 * 144^3: Sternheimer solves for the lowest band and two perturbations, FP64 at
   tolerance 1e-12 (Delta psi and Delta n within 1e-10) and STH_MIXED_BF16 at
-  1e-8 (Delta psi within 1e-6), against the oracle's PCG solutions stored in
+  1e-8 (Delta psi within 1e-6; the FP32 plane kernel of the same form), against
+  the oracle's PCG solutions stored in
   tests/oracle_data/ by tests/golden/make_response_cache.py from the oracle
   valence state of tests/golden/make_valence_cache.py; the oracle forms Delta n
   of that band from them.  The oracle's LOBPCG is run to residual 3e-9 at this
@@ -24,6 +27,7 @@ import pytest
 
 import oracle
 import oracle_store
+import tune_force
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -49,31 +53,34 @@ def _orthonormal_rows(npw, nv, seed):
     return np.ascontiguousarray(q.T)
 
 
+@pytest.mark.parametrize("kind", [2, 4])
 @pytest.mark.parametrize("name", ["cfg4c", "cfg5"])
-def test_apply_h_large_grid(sth, name):
+def test_apply_h_large_grid(sth, name, kind, monkeypatch, tmp_path):
     P, ctx = sth
     cfg = workloads.get_config(name)
     s = _system(name)
     psi = _orthonormal_rows(s.npw, 4, 3)
-    sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi,
-                           np.arange(4.0))
+    eps = np.arange(4.0)
+    info = tune_force.shape_info(P, ctx, cfg, s, psi, eps)
+    print(name, {k: v for k, v in info.items() if k != "tune_ms"})
+    if cfg.N > 96:   # only the tile-free forms run
+        assert info["plane_kernel_fp64"] in (2, 4) and info["plane_kernel_fp32"] in (2, 4)
+    sid = tune_force.system_with(P, ctx, monkeypatch, tmp_path / "tune.jsonl", cfg, s, psi, eps,
+                                 ((0, kind, 0), (0, kind, 0)), info)
     try:
-        info = P.sth_system_info_get(ctx, sid)
-        print(name, {k: v for k, v in info.items() if k != "tune_ms"})
-        if cfg.N > 96:   # only the strip form fits
-            assert info["plane_kernel_fp64"] == 2 and info["plane_kernel_fp32"] == 2
         rng = np.random.default_rng(31)
         c = rng.standard_normal((3, s.npw)) + 1j * rng.standard_normal((3, s.npw))
         got = P.sth_apply_h(ctx, sid, c)
         ref = oracle.apply_H(s, c)
         err = np.abs(got - ref).max() / np.abs(ref).max()
-        print(f"{name} (N={cfg.N}) H.psi rel err {err:.2e}")
+        print(f"{name} (N={cfg.N}) plane kind {kind}: H.psi rel err {err:.2e}")
         assert err < 1e-12
     finally:
         P.sth_release_system(ctx, sid)
 
 
-def test_solves_144_lowest_band(sth):
+@pytest.mark.parametrize("kind", [2, 4])
+def test_solves_144_lowest_band(sth, kind, monkeypatch, tmp_path):
     P, ctx = sth
     cfg = workloads.get_config("cfg5")
     eps, psi = oracle_store.valence("cfg5", nv=1)
@@ -84,7 +91,8 @@ def test_solves_144_lowest_band(sth):
     ref_dn = np.stack([oracle.drho(s, psi, ref_x[j][None]) for j in range(ref_x.shape[0])])
     npert = ref_x.shape[0]
     dv = workloads.dv_block(cfg, range(npert))
-    sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+    sid = tune_force.system_with(P, ctx, monkeypatch, tmp_path / "tune.jsonl", cfg, s, psi, eps,
+                                 ((0, kind, 0), (1, kind, 0)))
     try:
         t = P.sth_submit_solves(ctx, sid, dv, np.array([0]), tol=1e-12, want_dpsi=True)
         assert P.sth_wait(ctx, t, 120.0)
@@ -98,7 +106,7 @@ def test_solves_144_lowest_band(sth):
         e_x = max(np.linalg.norm(x[j, 0] - ref_x[j]) / np.linalg.norm(ref_x[j])
                   for j in range(npert))
         e_dn = np.abs(dn - ref_dn).max() / np.abs(ref_dn).max()
-        print(f"144^3 FP64: iterations {iters}, dpsi {e_x:.2e}, dn {e_dn:.2e}")
+        print(f"144^3 plane kind {kind} FP64: iterations {iters}, dpsi {e_x:.2e}, dn {e_dn:.2e}")
         assert e_x < 1e-10 and e_dn < 1e-10
         t = P.sth_submit_solves(ctx, sid, dv, np.array([0]), tol=1e-8,
                                 precision=P.STH_MIXED_BF16, want_dpsi=True)
@@ -109,7 +117,7 @@ def test_solves_144_lowest_band(sth):
         assert np.all(status == 0) and resid.max() <= 1e-8
         e_x = max(np.linalg.norm(x[j, 0] - ref_x[j]) / np.linalg.norm(ref_x[j])
                   for j in range(npert))
-        print(f"144^3 mixed-bf16: iterations {iters}, dpsi {e_x:.2e}")
+        print(f"144^3 plane kind {kind} mixed-bf16: iterations {iters}, dpsi {e_x:.2e}")
         assert e_x < 1e-6
     finally:
         P.sth_release_system(ctx, sid)

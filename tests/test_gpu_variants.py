@@ -2,60 +2,39 @@
 
 The autotuner keeps the fastest (radix plan, plane kernel form, z-stick kernel
 form) per precision, so a normal run exercises only one of them.  Here every radix
-plan and every kernel form of both stages (plane: workgroup, wave, strip and
-persistent forms; z-sticks: workgroup and wave forms) is forced through the tuning cache
-(STH_TUNE_CACHE) in FP64 and in FP32 and checked against the oracle: H.psi in FP64
-(1e-12 relative) and mixed-precision solves, whose inner operator uses the FP32
-variant (1e-6 relative on Delta psi at true residual 1e-8).  On config 1 also FP64
+plan and every kernel form of both stages (plane: workgroup, wave, strip,
+persistent and compact-row forms; z-sticks: workgroup and wave forms) is forced
+through the tuning cache (STH_TUNE_CACHE) in FP64 and in FP32 and checked
+against the oracle: H.psi in FP64 (1e-12 relative) and mixed-precision solves,
+whose inner operator uses the FP32 variant (1e-6 relative on Delta psi at true
+residual 1e-8).  On config 1 also FP64
 solves at 1e-12 with their Delta n (1e-10), which run psi_v(r) and Delta n
 through the FP64 form.  Config 1 (24^3, plans (8, 3) and (4, 6)) and the
 benchmark system (72^3, plans (8, 9) and (9, 8)).
 """
-import os
-
 import numpy as np
 import pytest
 
 import oracle
 import oracle_store
+import tune_force
 import workloads
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
-VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1, 2, 3)]
-
-
-def _force(path, info, M, plan, kind):
-    key = (f"gfx950 N={info['N']} npw={info['npw']} nst={info['nsticks']} M={M} "
-           f"slots={info['nslots']}")
-    with open(path, "a") as f:
-        f.write(f'{{"key": "{key}", "plan64": {plan}, "kind64": {kind}, "zkind64": {kind % 2}, '
-                f'"plan32": {plan}, "kind32": {kind}, "zkind32": {1 - kind % 2}, '
-                f'"kchunk": {info["gemm_kchunk"]}}}\n')
+VARIANTS = [(plan, kind) for plan in (0, 1) for kind in (0, 1, 2, 3, 4)]
 
 
 def _systems(P, ctx, monkeypatch, tmp_path, cfg, s, psi, eps, nv):
-    """Yields (plan, kind, system id) with the variant forced."""
-    base = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
-    info = P.sth_system_info_get(ctx, base)
-    info["N"] = cfg.N
-    P.sth_release_system(ctx, base)
-    M = nv + s.beta.shape[0]
+    """Yields (plan, kind, system id) with the variant forced (z-stick forms
+    alternate with the plane form, FP64 and FP32 opposite)."""
+    info = tune_force.shape_info(P, ctx, cfg, s, psi, eps)
     for plan, kind in VARIANTS:
         path = tmp_path / f"tune_{plan}_{kind}.jsonl"
-        _force(path, info, M, plan, kind)
-        monkeypatch.setenv("STH_TUNE_CACHE", str(path))
-        sid = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
-        got = P.sth_system_info_get(ctx, sid)
-        assert got["tuned_from_cache"] == 1
-        assert (got["fft_plan_fp64"], got["plane_kernel_fp64"], got["zfft_kernel_fp64"]) == \
-            (plan, kind, kind % 2)
-        assert (got["fft_plan_fp32"], got["plane_kernel_fp32"], got["zfft_kernel_fp32"]) == \
-            (plan, kind, 1 - kind % 2)
+        sid = tune_force.system_with(P, ctx, monkeypatch, path, cfg, s, psi, eps,
+                                     ((plan, kind, kind % 2), (plan, kind, 1 - kind % 2)), info)
         yield plan, kind, sid
         P.sth_release_system(ctx, sid)
-    monkeypatch.delenv("STH_TUNE_CACHE")
 
 
 def test_variants_cfg1(cfg1_system, cfg1_dense, monkeypatch, tmp_path):
