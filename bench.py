@@ -437,8 +437,14 @@ def run_workload(P, torch, name, npert, args, pool=None):
 
         def step(prec):
             t = P.sth_submit_solves(ctx, sid, dv, bands, tol=args.tol, precision=prec)
-            if not P.sth_wait(ctx, t, 3600.0):
-                raise RuntimeError("step did not finish")
+            # a long step reports its progress every 30 s (solves finished so far)
+            t_wait = time.perf_counter()
+            while not P.sth_wait(ctx, t, 30.0):
+                if time.perf_counter() - t_wait > 3600.0:
+                    raise RuntimeError("step did not finish")
+                info = P.sth_poll(ctx, t)
+                print(f"{name}: {info['n_finished']} of {info['n_total']} solves finished",
+                      file=sys.stderr, flush=True)
             it, res, st, lat = P.sth_fetch_stats(ctx, t, nsolves)
             P.sth_chi0_block(ctx, t, npert)
             P.sth_release_ticket(ctx, t)

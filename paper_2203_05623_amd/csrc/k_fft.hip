@@ -1243,13 +1243,16 @@ __global__ __launch_bounds__((Strips<N, T>::NT)) void k_plane_strips(
 // LDS rows are rotated by their index (element c of row f at f N + (c + f) mod N),
 // so that the L lanes of a column transform, which read L consecutive rows of
 // one column, hit distinct banks.
-template <int N>
+template <int N, typename T>
 struct RowsForm {
   static constexpr int L = (N % 16 == 0) ? 16 : 8;   // lanes per transform
   static constexpr int R = N / L;                      // elements per lane
   static constexpr int LOG2L = L == 16 ? 4 : 3;
-  // groups of L lanes per workgroup, so that the N columns split evenly
-  static constexpr int G = N == 144 ? 36 : (N == 96 ? 48 : (N == 72 ? 72 : (N == 48 ? 48 : 24)));
+  // groups of L lanes per workgroup, so that the N columns split evenly; the
+  // FP32 144^3 plane (81,792 B) takes 16 groups, so that two workgroups (LDS
+  // and registers) share a CU
+  static constexpr int G = N == 144 ? (sizeof(T) == 4 ? 16 : 36)
+                                    : (N == 96 ? 48 : (N == 72 ? 72 : (N == 48 ? 48 : 24)));
   static constexpr int NT = G * L;
   static_assert(NT % 64 == 0 && NT <= 1024, "workgroup shape");
   static_assert(R == 3 || R == 6 || R == 9, "in-lane radix");
@@ -1323,7 +1326,7 @@ __device__ inline cpx<T> lane_xor(cpx<T> v, int m) {
 // tw: the table exp(-2 pi i t / N).
 template <int N, typename T>
 struct LaneFFT {
-  using F = RowsForm<N>;
+  using F = RowsForm<N, T>;
   static constexpr int L = F::L, R = F::R;
   __device__ static int bitrev(int l) {
     return int(__builtin_bitreverse32(unsigned(l)) >> (32 - F::LOG2L));
@@ -1334,26 +1337,37 @@ struct LaneFFT {
     pass_twiddles<R>(tw, l, w);   // w[p] = w_N^(-l p); the inverse takes the conjugates
 #pragma unroll
     for (int p = 1; p < R; ++p) v[p] = v[p] * conj(w[p]);
+    // decimation in frequency, sign +: the top lane of a pair keeps a + b, the
+    // bottom one (a - b) w; both as (u + s v) w_s with s = +1, w_s = 1 on top
+    // and s = -1, w_s = w below (no select, one instruction stream)
 #pragma unroll
-    for (int h = L / 2; h >= 1; h >>= 1) {   // decimation in frequency, sign +
+    for (int h = L / 2; h >= 1; h >>= 1) {
       const bool bottom = (l & h) != 0;
+      const T sg = bottom ? T(-1) : T(1);
       const cpx<T> wt = conj(tw[(l & (h - 1)) * (N / (2 * h))]);
+      const cpx<T> ws = bottom ? wt : cpx<T>{T(1), T(0)};
 #pragma unroll
       for (int p = 0; p < R; ++p) {
         const cpx<T> u = lane_xor(v[p], h);
-        v[p] = bottom ? (u - v[p]) * wt : v[p] + u;
+        v[p] = cpx<T>{u.x + sg * v[p].x, u.y + sg * v[p].y} * ws;
       }
     }
   }
   __device__ static void forward(cpx<T> (&v)[R], const cpx<T>* tw, int l) {
+    // decimation in time, sign -: top a + b w, bottom a - b w.  Each lane
+    // scales its own value first (the bottom one by w, the top one by 1) and
+    // exchanges the product: z_partner + s z_self with s = +1 on top, -1 below.
 #pragma unroll
-    for (int h = 1; h < L; h <<= 1) {   // decimation in time, sign -
+    for (int h = 1; h < L; h <<= 1) {
       const bool bottom = (l & h) != 0;
+      const T sg = bottom ? T(-1) : T(1);
       const cpx<T> wt = tw[(l & (h - 1)) * (N / (2 * h))];
+      const cpx<T> ws = bottom ? wt : cpx<T>{T(1), T(0)};
 #pragma unroll
       for (int p = 0; p < R; ++p) {
-        const cpx<T> u = lane_xor(v[p], h);
-        v[p] = bottom ? u - v[p] * wt : v[p] + u * wt;
+        const cpx<T> z = v[p] * ws;
+        const cpx<T> zp = lane_xor(z, h);
+        v[p] = cpx<T>{zp.x + sg * z.x, zp.y + sg * z.y};
       }
     }
     cpx<T> w[R];
@@ -1376,10 +1390,10 @@ struct LaneFFT {
 // reads of one row stay inside one wavefront (in order); two workgroup
 // barriers per plane separate (A), (B) and (C).
 template <int N, typename T>
-__global__ __launch_bounds__((RowsForm<N>::NT)) void k_plane_rows(
+__global__ __launch_bounds__((RowsForm<N, T>::NT)) void k_plane_rows(
     GridDev g, VecSet<cpx<T>> sticks, const int* __restrict__ slots, int ncols, const T* pot,
     const T* const* __restrict__ pot_ptr) {
-  using F = RowsForm<N>;
+  using F = RowsForm<N, T>;
   using X = LaneFFT<N, T>;
   constexpr int L = F::L, R = F::R, G = F::G;
   extern __shared__ unsigned char smem_raw[];
@@ -1387,9 +1401,23 @@ __global__ __launch_bounds__((RowsForm<N>::NT)) void k_plane_rows(
   const int nrow = g.nrow;
   const int l = threadIdx.x % L, grp = threadIdx.x / L;
   const int lq = X::bitrev(l);
-  const cpx<T>* tw = twiddles<T>(g);
+  // compact row (+1, 0 for an empty row) of each i1 = l + L r this lane holds in
+  // a column transform, one byte each
+  unsigned fpk[(R + 3) / 4];
+#pragma unroll
+  for (int i = 0; i < (R + 3) / 4; ++i) fpk[i] = 0u;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    fpk[r >> 2] |= unsigned(compact_row(g, l + L * r) + 1) << (8 * (r & 3));
+  auto fof = [&](int r) { return int((fpk[r >> 2] >> (8 * (r & 3))) & 0xFFu) - 1; };
   const long long nplanes = (long long)ncols * N;
   for (long long q = blockIdx.x; q < nplanes; q += gridDim.x) {
+    // the twiddle pointer is opaque to the compiler per plane (an empty asm
+    // that claims to change it), so that the twiddle loads are redone per
+    // plane from the cache instead of being hoisted out of the loop into
+    // registers that would have to be spilled
+    const cpx<T>* tw = twiddles<T>(g);
+    asm volatile("" : "+s"(tw));
     const int c = int(q / N), i0 = int(q - (long long)c * N);
     const int slot = slots[c];
     cpx<T>* row = sticks.base + slot * sticks.stride + (long long)i0 * g.nst;
@@ -1417,7 +1445,7 @@ __global__ __launch_bounds__((RowsForm<N>::NT)) void k_plane_rows(
       cpx<T> v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int f = compact_row(g, l + L * r);
+        const int f = fof(r);
         v[r] = f >= 0 ? Y[f * N + rows_rot<N>(f, cc)] : cpx<T>{T(0), T(0)};
       }
       X::inverse(v, tw, l);
@@ -1426,7 +1454,7 @@ __global__ __launch_bounds__((RowsForm<N>::NT)) void k_plane_rows(
       X::forward(v, tw, l);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int f = compact_row(g, l + L * r);
+        const int f = fof(r);
         if (f >= 0) Y[f * N + rows_rot<N>(f, cc)] = v[r];
       }
     }
@@ -1660,14 +1688,14 @@ void launch_plane_rows(const GridDev& g, VecSet<cpx<T>> sticks, const int* slots
     if (it == per_cu_of.end()) {
       int b = 0;
       STH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &b, reinterpret_cast<const void*>(&k_plane_rows<N, T>), RowsForm<N>::NT, sm));
+          &b, reinterpret_cast<const void*>(&k_plane_rows<N, T>), RowsForm<N, T>::NT, sm));
       it = per_cu_of.emplace(sm, b > 0 ? b : 1).first;
     }
     per_cu = it->second;
   }
   const long long np = (long long)ncols * N;
   const dim3 pg((unsigned)std::min<long long>(np, (long long)per_cu * device_cus()));
-  hipLaunchKernelGGL((k_plane_rows<N, T>), pg, dim3(RowsForm<N>::NT), sm, st, g, sticks, slots,
+  hipLaunchKernelGGL((k_plane_rows<N, T>), pg, dim3(RowsForm<N, T>::NT), sm, st, g, sticks, slots,
                      ncols, pot, pot_ptr);
 }
 

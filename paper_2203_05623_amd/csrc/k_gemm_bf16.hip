@@ -14,6 +14,8 @@
 // v_mfma_f32_16x16x32_bf16 lane layout (64 lanes, l = lane), measured on gfx950:
 //   A[i][k]: i = l % 16, k = 8 (l / 16) + e (e < 8 bf16 values per lane);
 //   B[k][j]: k = 8 (l / 16) + e, j = l % 16;  D[i][j], register v: i = 4 (l / 16) + v, j = l % 16.
+#include <cstdlib>
+
 #include "errors.hpp"
 #include "kernels.hpp"
 
@@ -67,12 +69,24 @@ __device__ inline f4 acc3(bf8 a_hi, bf8 a_lo, bf8 b_hi, bf8 b_lo, f4 c) {
 }
 
 // part[s][c][m] = sum_{k in chunk s} conj(W[m][k]) B_c[k]
-// (registers budgeted for three workgroups per CU in both kernels)
-__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_ah_b_bf16(
+// Workgroup tile: 32 XT rows of W x 32 YT vectors; the 4 waves sit 2 x 2, each
+// holding 16 XT rows x 16 YT vectors (XT x YT MFMA tiles, real and imaginary
+// parts).  W is re-read once per column tile and the vectors once per row
+// tile, so the 128 x 128 tile (XT = YT = 4) streams half the bytes of 64 x 64;
+// its 128 accumulators per lane go to the accumulation registers, one wave
+// per SIMD.  The column base offsets sit in LDS so that the staging of 16
+// vectors per thread needs no 16 pointers in registers.
+template <int XT, int YT>
+__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 4 ? 1 : 3))) void k_gemm_ah_b_bf16(
     const bz* __restrict__ Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
     const int* slots, int ncols, int K, int kchunk, z32* part) {
-  __shared__ bz As[2][BT][BKP];
-  __shared__ bz Bs[2][BT][BKP];
+  constexpr int TM = 32 * XT, TN = 32 * YT;
+  constexpr int NWC = TM * BK * 2 / 4 / BTHR;   // 16-B chunks of W per thread per stage
+  constexpr int NPB = TN * BK / BTHR;           // vector elements per thread per stage
+  constexpr int WPP = TM * (BK / 4);            // chunks per plane
+  __shared__ bz As[2][TM][BKP];
+  __shared__ bz Bs[2][TN][BKP];
+  __shared__ long long colbase[TN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   // one K-chunk at a time over the whole chip; within it, the m-tiles that share
@@ -80,49 +94,49 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
   int tx, ty;
   xcd_tile2(false, tx, ty);
   const int s = blockIdx.z;
-  const int m0 = tx * BT, n0 = ty * BT;
+  const int m0 = tx * TM, n0 = ty * TN;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
   const int kq = lane >> 4, r16 = lane & 15;
-  f4 accr[2][2], acci[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
-  // staging: W as 16-B chunks (4 complex) of both planes, 4 per thread; the
-  // vectors as single complex values, 8 per thread
-  const z64* bcol[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int n = n0 + (tid + i * BTHR) / BK;
-    bcol[i] = (n < ncols) ? B.base + (long long)slots[n] * B.stride : nullptr;
+  for (int c = tid; c < TN; c += BTHR) {
+    const int n = n0 + c;
+    colbase[c] = n < ncols ? (long long)slots[n] * B.stride : -1ll;
   }
-  uint4 rw[4];
-  z64 rb[8];
+  __syncthreads();
+  f4 accr[XT][YT], acci[XT][YT];
+#pragma unroll
+  for (int a = 0; a < XT; ++a)
+#pragma unroll
+    for (int b = 0; b < YT; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
+  // staging: W as 16-B chunks (4 complex) of both planes; the vectors as single
+  // complex values (FP64 in memory, split while stored to LDS)
+  uint4 rw[NWC];
+  z64 rb[NPB];
   auto fetch = [&](int kb) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NWC; ++i) {
       const int c = tid + i * BTHR;
-      const int pl = c >> 9, row = (c & 511) >> 3, k4 = (c & 7) * 4;
+      const int pl = c / WPP, rem = c - pl * WPP, row = rem >> 3, k4 = (rem & 7) * 4;
       const int m = m0 + row;
       const bz* src = Wb + pl * wplane + (long long)m * ldw + kb + k4;
       rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int kk = (tid + i * BTHR) % BK, k = kb + kk;
-      rb[i] = (bcol[i] && k < kend) ? bcol[i][k] : z64{0.0, 0.0};
+    for (int i = 0; i < NPB; ++i) {
+      const int e = tid + i * BTHR, col = e / BK, k = kb + e % BK;
+      const long long cb = colbase[col];
+      rb[i] = (cb >= 0 && k < kend) ? B.base[cb + k] : z64{0.0, 0.0};
     }
   };
   if (kbeg < kend) fetch(kbeg);
   for (int kb = kbeg; kb < kend; kb += BK) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NWC; ++i) {
       const int c = tid + i * BTHR;
-      const int pl = c >> 9, row = (c & 511) >> 3, k4 = (c & 7) * 4;
+      const int pl = c / WPP, rem = c - pl * WPP, row = rem >> 3, k4 = (rem & 7) * 4;
       *reinterpret_cast<uint4*>(&As[pl][row][k4]) = rw[i];
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NPB; ++i) {
       const int e = tid + i * BTHR, col = e / BK, kk = e % BK;
       split(float(rb[i].x), float(rb[i].y), Bs[0][col][kk], Bs[1][col][kk]);
     }
@@ -131,63 +145,69 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ++ks) {
       const int k0 = ks * 16 + 4 * kq;
-      bf8 ah[2], al[2], bh[2], bl[2];
+      bf8 bh[YT], bl[YT];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        ah[t] = ld8(&As[0][wm * 32 + t * 16 + r16][k0]);
-        al[t] = ld8(&As[1][wm * 32 + t * 16 + r16][k0]);
-        bh[t] = ld8(&Bs[0][wn * 32 + t * 16 + r16][k0]);
-        bl[t] = ld8(&Bs[1][wn * 32 + t * 16 + r16][k0]);
+      for (int t = 0; t < YT; ++t) {
+        bh[t] = ld8(&Bs[0][wn * 16 * YT + t * 16 + r16][k0]);
+        bl[t] = ld8(&Bs[1][wn * 16 * YT + t * 16 + r16][k0]);
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < XT; ++x) {
+        const bf8 ah = ld8(&As[0][wm * 16 * XT + x * 16 + r16][k0]);
+        const bf8 al = ld8(&As[1][wm * 16 * XT + x * 16 + r16][k0]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int y = 0; y < YT; ++y) {
           // Re = sum W.x P.x + W.y P.y;  Im = sum W.x P.y - W.y P.x
-          accr[x][y] = acc3(ah[x], al[x], bh[y], bl[y], accr[x][y]);
-          acci[x][y] = acc3(ah[x], al[x], swap_neg_odd(bh[y]), swap_neg_odd(bl[y]), acci[x][y]);
+          accr[x][y] = acc3(ah, al, bh[y], bl[y], accr[x][y]);
+          acci[x][y] = acc3(ah, al, swap_neg_odd(bh[y]), swap_neg_odd(bl[y]), acci[x][y]);
         }
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XT; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < YT; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 32 + x * 16 + 4 * kq + v;
-        const int n = n0 + wn * 32 + y * 16 + r16;
+        const int m = m0 + wm * 16 * XT + x * 16 + 4 * kq + v;
+        const int n = n0 + wn * 16 * YT + y * 16 + r16;
         if (m < M && n < ncols)
           part[((long long)s * ncols + n) * M + m] = z32{accr[x][y][v], acci[x][y][v]};
       }
 }
 
 // Y_c[g] = s0 Y_c[g] + sum_m W[m][g] C[c][m]  (+ optional partial dots with dot_in)
-__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_a_c_bf16(
+// Workgroup tile: 64 rows g x 32 YT columns (each wave 32 g x 16 YT columns);
+// YT = 4 reads W once per 128 columns instead of once per 64.
+template <int YT>
+__global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2 : 3))) void k_gemm_a_c_bf16(
     const bz* __restrict__ Wb, long long wplane, int ldw, int M, const z32* __restrict__ C,
     VecSet<z64> Y, const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
     double* dots) {
+  constexpr int TN = 32 * YT;
+  constexpr int NC = TN * BK / BTHR;   // C elements per thread per stage
   __shared__ bz As[2][BT][BKP];   // [plane][g][m]: W staged transposed
-  __shared__ bz Cs[2][BT][BKP];   // [plane][column][m]
-  __shared__ double red[2][BT];
+  __shared__ bz Cs[2][TN][BKP];   // [plane][column][m]
+  __shared__ double red[YT][32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = wave & 1, wn = wave >> 1;
   // the column tiles that share a block of W rows run on one XCD, one after the
   // other, so that block is read from memory once
   int tx, ty;
   xcd_tile2(true, tx, ty);
-  const int g0 = tx * BT, n0 = ty * BT;
+  const int g0 = tx * BT, n0 = ty * TN;
   const int kq = lane >> 4, r16 = lane & 15;
-  f4 accr[2][2], acci[2][2];
+  f4 accr[2][YT], acci[2][YT];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
+    for (int b = 0; b < YT; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
   // staging: W rows m (both planes) as 16-B chunks of 4 consecutive g, 4 per
-  // thread, written transposed; C as single complex values, 8 per thread
+  // thread, written transposed; C as single complex values
   uint4 rw[4];
-  z32 rc[8];
+  z32 rc[NC];
   auto fetch = [&](int mb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -198,7 +218,7 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
       rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NC; ++i) {
       const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
       const int n = n0 + col, m = mb + mm;
       rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : z32{0.f, 0.f};
@@ -215,7 +235,7 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
       for (int u = 0; u < 4; ++u) As[pl][g4 + u][mm] = q[u];
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NC; ++i) {
       const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
       split(rc[i].x, rc[i].y, Cs[0][col][mm], Cs[1][col][mm]);
     }
@@ -224,29 +244,32 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ++ks) {
       const int k0 = ks * 16 + 4 * kq;
-      bf8 ah[2], al[2], ch[2], cl[2];
+      bf8 ah[2], al[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         ah[t] = ld8(&As[0][wg * 32 + t * 16 + r16][k0]);
         al[t] = ld8(&As[1][wg * 32 + t * 16 + r16][k0]);
-        ch[t] = ld8(&Cs[0][wn * 32 + t * 16 + r16][k0]);
-        cl[t] = ld8(&Cs[1][wn * 32 + t * 16 + r16][k0]);
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < YT; ++y) {
+        const bf8 ch = ld8(&Cs[0][wn * 16 * YT + y * 16 + r16][k0]);
+        const bf8 cl = ld8(&Cs[1][wn * 16 * YT + y * 16 + r16][k0]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int x = 0; x < 2; ++x) {
           // Re = sum W.x C.x - W.y C.y;  Im = sum W.x C.y + W.y C.x
-          accr[x][y] = acc3(ah[x], al[x], neg_odd(ch[y]), neg_odd(cl[y]), accr[x][y]);
-          acci[x][y] = acc3(ah[x], al[x], swap(ch[y]), swap(cl[y]), acci[x][y]);
+          accr[x][y] = acc3(ah[x], al[x], neg_odd(ch), neg_odd(cl), accr[x][y]);
+          acci[x][y] = acc3(ah[x], al[x], swap(ch), swap(cl), acci[x][y]);
         }
+      }
     }
     __syncthreads();
   }
-  double dsum[2] = {0.0, 0.0};
+  double dsum[YT];
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    const int n = n0 + wn * 32 + y * 16 + r16;
+  for (int y = 0; y < YT; ++y) dsum[y] = 0.0;
+#pragma unroll
+  for (int y = 0; y < YT; ++y) {
+    const int n = n0 + wn * 16 * YT + y * 16 + r16;
     if (n >= ncols) continue;
     z64* yrow = Y.base + (long long)slots[n] * Y.stride;
     const z64* drow = dots ? dot_in.base + (long long)slots[n] * dot_in.stride : nullptr;
@@ -273,20 +296,20 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(3))) void 
   if (!dots) return;
   // sum over the 4 lane groups that share a column, then over the two g halves
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
+  for (int y = 0; y < YT; ++y) {
     dsum[y] += __shfl_xor(dsum[y], 16);
     dsum[y] += __shfl_xor(dsum[y], 32);
   }
   if (wg == 1 && kq == 0) {
-    red[0][wn * 32 + r16] = dsum[0];
-    red[1][wn * 32 + r16] = dsum[1];
+#pragma unroll
+    for (int y = 0; y < YT; ++y) red[y][wn * 16 + r16] = dsum[y];
   }
   __syncthreads();
   if (wg == 0 && kq == 0) {
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int n = n0 + wn * 32 + y * 16 + r16;
-      if (n < ncols) dots[(long long)n * gridDim.x + tx] = dsum[y] + red[y][wn * 32 + r16];
+    for (int y = 0; y < YT; ++y) {
+      const int n = n0 + wn * 16 * YT + y * 16 + r16;
+      if (n < ncols) dots[(long long)n * gridDim.x + tx] = dsum[y] + red[y][wn * 16 + r16];
     }
   }
 }
@@ -311,6 +334,20 @@ void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st)
   STH_HIP_CHECK(hipGetLastError());
 }
 
+// Tile choice (environment STH_BF16_TILE): 0 = 64 x 64 tiles for both
+// products; 1 (default) = 64 x 128 for Y += W C once 256 columns fill it; 2 =
+// also 128 x 128 for C = W^H B.  On the 144^3 system (2048 columns, M = 2048)
+// the wide Y += W C tile took 2.4% off that phase, while the 128 x 128
+// C = W^H B tile, held to one wave per SIMD by its 450 registers, ran no
+// faster than 64 x 64 at three.
+int bf16_tile() {
+  static const int t = [] {
+    const char* e = std::getenv("STH_BF16_TILE");
+    return e ? std::atoi(e) : 1;
+  }();
+  return t;
+}
+
 void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
                            const int* slots, int ncols, int K, int kchunk, z32* part,
                            hipStream_t st) {
@@ -321,9 +358,15 @@ void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSe
     throw Error(STH_E_INTERNAL);
   }
   const int nsplit = (K + kchunk - 1) / kchunk;
-  dim3 grid((M + BT - 1) / BT, (ncols + BT - 1) / BT, nsplit);
-  hipLaunchKernelGGL(k_gemm_ah_b_bf16, grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
-                     slots, ncols, K, kchunk, part);
+  if (bf16_tile() >= 2 && ncols >= 256 && M >= 256) {
+    dim3 grid((M + 127) / 128, (ncols + 127) / 128, nsplit);
+    hipLaunchKernelGGL((k_gemm_ah_b_bf16<4, 4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
+                       slots, ncols, K, kchunk, part);
+  } else {
+    dim3 grid((M + BT - 1) / BT, (ncols + BT - 1) / BT, nsplit);
+    hipLaunchKernelGGL((k_gemm_ah_b_bf16<2, 2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
+                       slots, ncols, K, kchunk, part);
+  }
   STH_HIP_CHECK(hipGetLastError());
 }
 
@@ -335,9 +378,15 @@ void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const 
     set_error("bf16 GEMM: row pitch %d (want %d)", ldw, bf16_ldw(K));
     throw Error(STH_E_INTERNAL);
   }
-  dim3 grid(gemm_a_c_tiles(K), (ncols + BT - 1) / BT);
-  hipLaunchKernelGGL(k_gemm_a_c_bf16, grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C,
-                     Y, slots, ncols, K, s0, dot_in, dots);
+  if (bf16_tile() >= 1 && ncols >= 256) {
+    dim3 grid(gemm_a_c_tiles(K), (ncols + 127) / 128);
+    hipLaunchKernelGGL((k_gemm_a_c_bf16<4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C, Y,
+                       slots, ncols, K, s0, dot_in, dots);
+  } else {
+    dim3 grid(gemm_a_c_tiles(K), (ncols + BT - 1) / BT);
+    hipLaunchKernelGGL((k_gemm_a_c_bf16<2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C, Y,
+                       slots, ncols, K, s0, dot_in, dots);
+  }
   STH_HIP_CHECK(hipGetLastError());
 }
 
