@@ -42,9 +42,12 @@ MI355X_BF16_TFLOPS = 2500.0   # BF16 dense MFMA
 # summaries and commands); entries are dropped whenever those kernels change
 HBM_OVER_ALGORITHMIC = {
     # 144^3: split-K projector GEMM (W and P tiles re-read per row / column tile)
-    ("cfg5", "gemm_ah_b", "fp64"): 4.744,
-    # 144^3 strip-form plane kernels (scratch plane Y in HBM between directions)
-    ("cfg5", "plane", "fp64"): 7.421, ("cfg5", "plane", "mixed-bf16"): 6.536,
+    ("cfg5", "gemm_ah_b", "fp64"): 4.796,
+    # 144^3 compact-row plane kernels (FP64; FP32 and FP64 in the mixed form)
+    ("cfg5", "plane", "fp64"): 1.914, ("cfg5", "plane", "mixed-bf16"): 1.304,
+    # 72^3 single-pass plane kernels (persistent form FP64, workgroup form FP32)
+    ("cfg2", "plane", "fp64"): 1.005, ("cfg2", "plane", "mixed-bf16"): 1.009,
+    ("cfg2", "gemm_ah_b", "fp64"): 1.852,
 }
 # --precision: FP64 solves; mixed (FP32 inner operator, FP32-MFMA projector
 # GEMMs); mixed-bf16 (FP32 inner operator, BF16-MFMA hi/lo projector GEMMs)
@@ -169,7 +172,10 @@ class OraclePool:
 
     def close(self):
         import shutil
-        self.pool.terminate()
+        # idle workers leave on their own (no signal: a profiler's handler in a
+        # forked worker would report a termination signal as a crash)
+        self.pool.close()
+        self.pool.join()
         shutil.rmtree(self.scratch, ignore_errors=True)
 
 

@@ -389,6 +389,11 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
   s.d_stage = DevMem(&budget_, (size_t)kStageSlots * s.nrow * N * sizeof(z64));
   s.g.stage = s.d_stage.as<void>();
   s.g.stage_slots = kStageSlots;
+  // before (or without) the autotuner, grids whose plane tile exceeds the LDS
+  // take the compact-row form where its rows fit (the valence set-up runs here)
+  for (int k = 0; k < 2; ++k)
+    if (N > kTileMaxN && plane_kind_available(s.g, kPlaneRows, k == 1))
+      s.g.plane_kind[k] = kPlaneRows;
   prepare_fft_kernels(N);
   // split-K chunk of C = W^H P: the smallest candidate of the autotuner (at most
   // kMaxSplit chunks, a multiple of the 16-element LDS stage); the partial
@@ -656,8 +661,13 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
                               s.ss.eps, st_);
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   h = prof_begin(PH_GEMM_AHB);
+  // the stick buffer is free once the forward z-FFTs have read it: it holds
+  // the bf16 split of the vectors, then of C
+  bz* split_scratch = reinterpret_cast<bz*>(s.d_sticks.as<z64>());
+  const size_t split_bytes = s.d_sticks.bytes();
   if (bf16)
-    launch_gemm_ah_b_bf16(wb, wplane, ldw, M, in, dl, n, s.npw, s.kchunk, part, st_);
+    launch_gemm_ah_b_bf16(wb, wplane, ldw, M, in, dl, n, s.npw, s.kchunk, part, split_scratch,
+                          split_bytes, st_);
   else
     launch_gemm_ah_b(w32, s.npw, M, in, dl, n, s.npw, s.kchunk, part, st_);
   prof_end(h, M * vb / 2 + n * vb, gf);
@@ -667,7 +677,8 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   h = prof_begin(PH_GEMM_AC);
   if (bf16)
     launch_gemm_a_c_bf16(wb, wplane, ldw, M, C, out, dl, n, s.npw, 1.0, in,
-                         dots ? s.d_dots.as<double>() : nullptr, st_);
+                         dots ? s.d_dots.as<double>() : nullptr, split_scratch, split_bytes,
+                         st_);
   else
     launch_gemm_a_c(w32, s.npw, M, C, out, dl, n, s.npw, 1.0, in,
                     dots ? s.d_dots.as<double>() : nullptr, st_);

@@ -71,22 +71,23 @@ __device__ inline f4 acc3(bf8 a_hi, bf8 a_lo, bf8 b_hi, bf8 b_lo, f4 c) {
 // part[s][c][m] = sum_{k in chunk s} conj(W[m][k]) B_c[k]
 // Workgroup tile: 32 XT rows of W x 32 YT vectors; the 4 waves sit 2 x 2, each
 // holding 16 XT rows x 16 YT vectors (XT x YT MFMA tiles, real and imaginary
-// parts).  W is re-read once per column tile and the vectors once per row
-// tile, so the 128 x 128 tile (XT = YT = 4) streams half the bytes of 64 x 64;
-// its 128 accumulators per lane go to the accumulation registers, one wave
-// per SIMD.  The column base offsets sit in LDS so that the staging of 16
-// vectors per thread needs no 16 pointers in registers.
+// parts).  Both operands come as bf16 hi/lo planes with rows padded to ldw:
+// W split once per system, the vectors split once per product by
+// k_split_cols (instead of once per row tile of every workgroup, whose FP64
+// loads and conversions kept the vector ALU busier than the matrix cores), so
+// staging is 16-byte copies.  A 4-complex chunk lies wholly inside or outside
+// [kbeg, kend) (both multiples of 4), and chunks of B past kend are zeroed.
 template <int XT, int YT>
 __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 4 ? 1 : 3))) void k_gemm_ah_b_bf16(
-    const bz* __restrict__ Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
-    const int* slots, int ncols, int K, int kchunk, z32* part) {
+    const bz* __restrict__ Wb, long long wplane, int ldw, int M, const bz* __restrict__ Pb,
+    long long pplane, int ncols, int K, int kchunk, z32* part) {
   constexpr int TM = 32 * XT, TN = 32 * YT;
   constexpr int NWC = TM * BK * 2 / 4 / BTHR;   // 16-B chunks of W per thread per stage
-  constexpr int NPB = TN * BK / BTHR;           // vector elements per thread per stage
+  constexpr int NPC = TN * BK * 2 / 4 / BTHR;   // 16-B chunks of the vectors
   constexpr int WPP = TM * (BK / 4);            // chunks per plane
+  constexpr int PPP = TN * (BK / 4);
   __shared__ bz As[2][TM][BKP];
   __shared__ bz Bs[2][TN][BKP];
-  __shared__ long long colbase[TN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   // one K-chunk at a time over the whole chip; within it, the m-tiles that share
@@ -97,20 +98,12 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 
   const int m0 = tx * TM, n0 = ty * TN;
   const int kbeg = s * kchunk, kend = min(K, kbeg + kchunk);
   const int kq = lane >> 4, r16 = lane & 15;
-  for (int c = tid; c < TN; c += BTHR) {
-    const int n = n0 + c;
-    colbase[c] = n < ncols ? (long long)slots[n] * B.stride : -1ll;
-  }
-  __syncthreads();
   f4 accr[XT][YT], acci[XT][YT];
 #pragma unroll
   for (int a = 0; a < XT; ++a)
 #pragma unroll
     for (int b = 0; b < YT; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
-  // staging: W as 16-B chunks (4 complex) of both planes; the vectors as single
-  // complex values (FP64 in memory, split while stored to LDS)
-  uint4 rw[NWC];
-  z64 rb[NPB];
+  uint4 rw[NWC], rb[NPC];
   auto fetch = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < NWC; ++i) {
@@ -121,10 +114,13 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 
       rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int i = 0; i < NPB; ++i) {
-      const int e = tid + i * BTHR, col = e / BK, k = kb + e % BK;
-      const long long cb = colbase[col];
-      rb[i] = (cb >= 0 && k < kend) ? B.base[cb + k] : z64{0.0, 0.0};
+    for (int i = 0; i < NPC; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c / PPP, rem = c - pl * PPP, col = rem >> 3, k4 = (rem & 7) * 4;
+      const int n = n0 + col;
+      const bz* src = Pb + pl * pplane + (long long)n * ldw + kb + k4;
+      rb[i] = (n < ncols && kb + k4 < kend) ? *reinterpret_cast<const uint4*>(src)
+                                             : uint4{0, 0, 0, 0};
     }
   };
   if (kbeg < kend) fetch(kbeg);
@@ -136,20 +132,23 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 
       *reinterpret_cast<uint4*>(&As[pl][row][k4]) = rw[i];
     }
 #pragma unroll
-    for (int i = 0; i < NPB; ++i) {
-      const int e = tid + i * BTHR, col = e / BK, kk = e % BK;
-      split(float(rb[i].x), float(rb[i].y), Bs[0][col][kk], Bs[1][col][kk]);
+    for (int i = 0; i < NPC; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c / PPP, rem = c - pl * PPP, col = rem >> 3, k4 = (rem & 7) * 4;
+      *reinterpret_cast<uint4*>(&Bs[pl][col][k4]) = rb[i];
     }
     __syncthreads();
     if (kb + BK < kend) fetch(kb + BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 16; ++ks) {
       const int k0 = ks * 16 + 4 * kq;
-      bf8 bh[YT], bl[YT];
+      bf8 bh[YT], bl[YT], bhs[YT], bls[YT];
 #pragma unroll
       for (int t = 0; t < YT; ++t) {
         bh[t] = ld8(&Bs[0][wn * 16 * YT + t * 16 + r16][k0]);
         bl[t] = ld8(&Bs[1][wn * 16 * YT + t * 16 + r16][k0]);
+        bhs[t] = swap_neg_odd(bh[t]);
+        bls[t] = swap_neg_odd(bl[t]);
       }
 #pragma unroll
       for (int x = 0; x < XT; ++x) {
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 
         for (int y = 0; y < YT; ++y) {
           // Re = sum W.x P.x + W.y P.y;  Im = sum W.x P.y - W.y P.x
           accr[x][y] = acc3(ah, al, bh[y], bl[y], accr[x][y]);
-          acci[x][y] = acc3(ah, al, swap_neg_odd(bh[y]), swap_neg_odd(bl[y]), acci[x][y]);
+          acci[x][y] = acc3(ah, al, bhs[y], bls[y], acci[x][y]);
         }
       }
     }
@@ -181,13 +180,17 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(XT * YT > 
 // Y_c[g] = s0 Y_c[g] + sum_m W[m][g] C[c][m]  (+ optional partial dots with dot_in)
 // Workgroup tile: 64 rows g x 32 YT columns (each wave 32 g x 16 YT columns);
 // YT = 4 reads W once per 128 columns instead of once per 64.
+// C comes split as bf16 hi/lo planes Cb[plane][column][Mp] (k_split_c, rows
+// zero-padded to Mp, a multiple of BK), staged by 16-byte copies.
 template <int YT>
 __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2 : 3))) void k_gemm_a_c_bf16(
-    const bz* __restrict__ Wb, long long wplane, int ldw, int M, const z32* __restrict__ C,
-    VecSet<z64> Y, const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
-    double* dots) {
+    const bz* __restrict__ Wb, long long wplane, int ldw, int M, const bz* __restrict__ Cb,
+    int Mp, VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
+    VecSet<const z64> dot_in, double* dots) {
   constexpr int TN = 32 * YT;
-  constexpr int NC = TN * BK / BTHR;   // C elements per thread per stage
+  constexpr int NCC = TN * BK * 2 / 4 / BTHR;   // 16-B chunks of C per thread per stage
+  constexpr int CPP = TN * (BK / 4);             // chunks per plane
+  const long long cplane = (long long)ncols * Mp;
   __shared__ bz As[2][BT][BKP];   // [plane][g][m]: W staged transposed
   __shared__ bz Cs[2][TN][BKP];   // [plane][column][m]
   __shared__ double red[YT][32];
@@ -205,9 +208,8 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2
 #pragma unroll
     for (int b = 0; b < YT; ++b) accr[a][b] = acci[a][b] = f4{0, 0, 0, 0};
   // staging: W rows m (both planes) as 16-B chunks of 4 consecutive g, 4 per
-  // thread, written transposed; C as single complex values
-  uint4 rw[4];
-  z32 rc[NC];
+  // thread, written transposed; C as 16-B chunks of 4 consecutive m
+  uint4 rw[4], rc[NCC];
   auto fetch = [&](int mb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -218,10 +220,12 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2
       rw[i] = (m < M) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
-      const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
-      const int n = n0 + col, m = mb + mm;
-      rc[i] = (n < ncols && m < M) ? C[(long long)n * M + m] : z32{0.f, 0.f};
+    for (int i = 0; i < NCC; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c / CPP, rem = c - pl * CPP, col = rem >> 3, m4 = (rem & 7) * 4;
+      const int n = n0 + col;
+      const bz* src = Cb + pl * cplane + (long long)n * Mp + mb + m4;
+      rc[i] = (n < ncols) ? *reinterpret_cast<const uint4*>(src) : uint4{0, 0, 0, 0};
     }
   };
   if (M > 0) fetch(0);
@@ -235,9 +239,10 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2
       for (int u = 0; u < 4; ++u) As[pl][g4 + u][mm] = q[u];
     }
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
-      const int e = tid + i * BTHR, col = e / BK, mm = e % BK;
-      split(rc[i].x, rc[i].y, Cs[0][col][mm], Cs[1][col][mm]);
+    for (int i = 0; i < NCC; ++i) {
+      const int c = tid + i * BTHR;
+      const int pl = c / CPP, rem = c - pl * CPP, col = rem >> 3, m4 = (rem & 7) * 4;
+      *reinterpret_cast<uint4*>(&Cs[pl][col][m4]) = rc[i];
     }
     __syncthreads();
     if (mb + BK < M) fetch(mb + BK);
@@ -254,11 +259,12 @@ __global__ __launch_bounds__(BTHR) __attribute__((amdgpu_waves_per_eu(YT > 2 ? 2
       for (int y = 0; y < YT; ++y) {
         const bf8 ch = ld8(&Cs[0][wn * 16 * YT + y * 16 + r16][k0]);
         const bf8 cl = ld8(&Cs[1][wn * 16 * YT + y * 16 + r16][k0]);
+        const bf8 chn = neg_odd(ch), cln = neg_odd(cl), chs = swap(ch), cls = swap(cl);
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           // Re = sum W.x C.x - W.y C.y;  Im = sum W.x C.y + W.y C.x
-          accr[x][y] = acc3(ah[x], al[x], neg_odd(ch), neg_odd(cl), accr[x][y]);
-          acci[x][y] = acc3(ah[x], al[x], swap(ch), swap(cl), acci[x][y]);
+          accr[x][y] = acc3(ah[x], al[x], chn, cln, accr[x][y]);
+          acci[x][y] = acc3(ah[x], al[x], chs, cls, acci[x][y]);
         }
       }
     }
@@ -324,6 +330,28 @@ __global__ void k_split_w(const z32* __restrict__ W, int M, int K, int ldw, bz* 
   split(v.x, v.y, Wb[i], Wb[wplane + i]);
 }
 
+// hi / lo planes of the listed FP64 vectors, Pb[plane][c][ldw] for list entry
+// c (rows zero-padded past K)
+__global__ void k_split_cols(VecSet<const z64> B, const int* slots, int K, int ldw, bz* Pb,
+                             long long pplane) {
+  const int c = blockIdx.y;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ldw) return;
+  const z64 v = g < K ? B.base[(long long)slots[c] * B.stride + g] : z64{0.0, 0.0};
+  const long long i = (long long)c * ldw + g;
+  split(float(v.x), float(v.y), Pb[i], Pb[pplane + i]);
+}
+
+// hi / lo planes of C[c][m] (FP32), Cb[plane][c][Mp] with rows zero-padded past M
+__global__ void k_split_c(const z32* __restrict__ C, int M, int Mp, bz* Cb, long long cplane) {
+  const int c = blockIdx.y;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= Mp) return;
+  const z32 v = m < M ? C[(long long)c * M + m] : z32{0.f, 0.f};
+  const long long i = (long long)c * Mp + m;
+  split(v.x, v.y, Cb[i], Cb[cplane + i]);
+}
+
 }  // namespace
 
 void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st) {
@@ -350,42 +378,52 @@ int bf16_tile() {
 
 void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
                            const int* slots, int ncols, int K, int kchunk, z32* part,
-                           hipStream_t st) {
+                           bz* scratch, size_t scratch_bytes, hipStream_t st) {
   if (ncols <= 0 || M <= 0) return;
-  if (ldw != bf16_ldw(K) || kchunk % 4 != 0) {
-    set_error("bf16 GEMM: row pitch %d (want %d), K chunk %d (multiple of 4)", ldw, bf16_ldw(K),
-              kchunk);
+  const long long pplane = (long long)ncols * ldw;
+  if (ldw != bf16_ldw(K) || kchunk % 4 != 0 || size_t(2 * pplane) * sizeof(bz) > scratch_bytes) {
+    set_error("bf16 GEMM: row pitch %d (want %d), K chunk %d (multiple of 4), scratch %zu B",
+              ldw, bf16_ldw(K), kchunk, scratch_bytes);
     throw Error(STH_E_INTERNAL);
   }
+  hipLaunchKernelGGL(k_split_cols, dim3((unsigned)((ldw + 255) / 256), (unsigned)ncols),
+                     dim3(256), 0, st, B, slots, K, ldw, scratch, pplane);
   const int nsplit = (K + kchunk - 1) / kchunk;
   if (bf16_tile() >= 2 && ncols >= 256 && M >= 256) {
     dim3 grid((M + 127) / 128, (ncols + 127) / 128, nsplit);
-    hipLaunchKernelGGL((k_gemm_ah_b_bf16<4, 4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
-                       slots, ncols, K, kchunk, part);
+    hipLaunchKernelGGL((k_gemm_ah_b_bf16<4, 4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M,
+                       scratch, pplane, ncols, K, kchunk, part);
   } else {
     dim3 grid((M + BT - 1) / BT, (ncols + BT - 1) / BT, nsplit);
-    hipLaunchKernelGGL((k_gemm_ah_b_bf16<2, 2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, B,
-                       slots, ncols, K, kchunk, part);
+    hipLaunchKernelGGL((k_gemm_ah_b_bf16<2, 2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M,
+                       scratch, pplane, ncols, K, kchunk, part);
   }
   STH_HIP_CHECK(hipGetLastError());
 }
 
 void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const z32* C,
                           VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
-                          VecSet<const z64> dot_in, double* dots, hipStream_t st) {
+                          VecSet<const z64> dot_in, double* dots, bz* scratch,
+                          size_t scratch_bytes, hipStream_t st) {
   if (ncols <= 0) return;
-  if (ldw != bf16_ldw(K)) {
-    set_error("bf16 GEMM: row pitch %d (want %d)", ldw, bf16_ldw(K));
+  const int Mp = ((M + BK - 1) / BK) * BK;
+  const long long cplane = (long long)ncols * Mp;
+  if (ldw != bf16_ldw(K) || size_t(2 * cplane) * sizeof(bz) > scratch_bytes) {
+    set_error("bf16 GEMM: row pitch %d (want %d), scratch %zu B", ldw, bf16_ldw(K),
+              scratch_bytes);
     throw Error(STH_E_INTERNAL);
   }
+  if (Mp > 0)
+    hipLaunchKernelGGL(k_split_c, dim3((unsigned)((Mp + 255) / 256), (unsigned)ncols),
+                       dim3(256), 0, st, C, M, Mp, scratch, cplane);
   if (bf16_tile() >= 1 && ncols >= 256) {
     dim3 grid(gemm_a_c_tiles(K), (ncols + 127) / 128);
-    hipLaunchKernelGGL((k_gemm_a_c_bf16<4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C, Y,
-                       slots, ncols, K, s0, dot_in, dots);
+    hipLaunchKernelGGL((k_gemm_a_c_bf16<4>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M,
+                       scratch, Mp, Y, slots, ncols, K, s0, dot_in, dots);
   } else {
     dim3 grid(gemm_a_c_tiles(K), (ncols + BT - 1) / BT);
-    hipLaunchKernelGGL((k_gemm_a_c_bf16<2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M, C, Y,
-                       slots, ncols, K, s0, dot_in, dots);
+    hipLaunchKernelGGL((k_gemm_a_c_bf16<2>), grid, dim3(BTHR), 0, st, Wb, wplane, ldw, M,
+                       scratch, Mp, Y, slots, ncols, K, s0, dot_in, dots);
   }
   STH_HIP_CHECK(hipGetLastError());
 }

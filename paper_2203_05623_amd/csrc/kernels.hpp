@@ -115,13 +115,17 @@ struct bz {
 // row pitch of the bf16 planes: a multiple of 64 with a full LDS stage of slack
 inline int bf16_ldw(int K) { return ((K + 63) / 64) * 64 + 64; }
 void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st);
-// Wb: the hi plane of the rows used; the lo plane starts wplane elements later
+// Wb: the hi plane of the rows used; the lo plane starts wplane elements later.
+// scratch (scratch_bytes): device memory free for the call, where the vectors
+// (2 ncols ldw bz) or C (2 ncols Mp bz, Mp = M rounded up to 32) are split
+// into bf16 hi/lo planes once before the product.
 void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
                            const int* slots, int ncols, int K, int kchunk, z32* part,
-                           hipStream_t st);
+                           bz* scratch, size_t scratch_bytes, hipStream_t st);
 void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const z32* C,
                           VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
-                          VecSet<const z64> dot_in, double* dots, hipStream_t st);
+                          VecSet<const z64> dot_in, double* dots, bz* scratch,
+                          size_t scratch_bytes, hipStream_t st);
 
 // ---- CG vector kernels (FP64) ----
 struct SlotState {
