@@ -103,6 +103,16 @@ typedef struct {
   const double* eps_v;      /* [nv] band energies (Ha), ascending */
   double spin_factor;       /* f_s in dn; 2.0 for a spin-unpolarised system */
   int ptr_kind;             /* of vloc_r, beta, dij, psi_v, eps_v */
+  int gamma_only;           /* 1: Gamma-point system (Section 3), every coefficient
+                               vector real in real space, c(-G) = conj c(G): the
+                               projector products of the solves run on half the
+                               sphere (C = 2 Re sum over G = 0 and the half after it,
+                               minus the G = 0 term; Y(-G) = conj Y(G)).  The sphere
+                               must hold -G with every G, and psi_v and beta must be
+                               so symmetric (within 1e-10 of their largest
+                               coefficient), else STH_E_INVALID; the right-hand
+                               sides are then symmetric since vloc_r and dV are
+                               real.  0: general complex vectors. */
 } sth_system_desc;
 
 typedef struct {

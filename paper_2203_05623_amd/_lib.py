@@ -40,7 +40,8 @@ class sth_system_desc(C.Structure):
     _fields_ = [("L", C.c_double), ("n", C.c_int), ("npw", C.c_int),
                 ("miller", C.POINTER(C.c_int32)), ("vloc_r", C.c_void_p), ("nproj", C.c_int),
                 ("beta", C.c_void_p), ("dij", C.c_void_p), ("nv", C.c_int), ("psi_v", C.c_void_p),
-                ("eps_v", C.c_void_p), ("spin_factor", C.c_double), ("ptr_kind", C.c_int)]
+                ("eps_v", C.c_void_p), ("spin_factor", C.c_double), ("ptr_kind", C.c_int),
+                ("gamma_only", C.c_int)]
 
 
 class sth_solve_opts(C.Structure):
@@ -231,8 +232,10 @@ def _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor):
     return d, keep
 
 
-def sth_set_system(ctx, L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor=2.0):
+def sth_set_system(ctx, L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor=2.0,
+                   gamma_only=False):
     d, keep = _desc(L, n, miller, vloc_r, beta, dij, psi_v, eps_v, spin_factor)
+    d.gamma_only = 1 if gamma_only else 0
     sid = C.c_int32()
     _check(lib().sth_set_system(ctx, C.byref(d), _stream(vloc_r), C.byref(sid)))
     del keep

@@ -15,7 +15,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["k_fft.hip", "k_gemm.hip", "k_gemm_bf16.hip", "k_cg.hip", "k_eig.hip", "k_pdep.hip",
            "k_lanczos.hip", "engine.cpp", "valence.cpp", "tune.cpp", "pdep.cpp", "lanczos.cpp",
-           "noalloc.cpp", "api.cpp"]
+           "noalloc.cpp", "k_gamma.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -307,6 +307,91 @@ int* Context::upload_list(System& s, const std::vector<int>& v) {
   return d;
 }
 
+// Gamma-point systems: the internal index k0 of G = 0, the internal index of
+// -G for every element after it (the stick-major order puts the sticks of
+// negative (m1, m2) and the negative m0 half of the (0, 0) stick before G = 0,
+// their mirrors after it), and a check that psi_v and beta are real in real
+// space (W(-G) = conj W(G) and Im W(0) = 0 within 1e-10 of the row's largest
+// coefficient).
+void Context::setup_gamma(System& s, const sth_system_desc& d, const StickBuild& sb) {
+  const int npw = s.npw;
+  std::vector<int> user_of(npw);
+  for (int u = 0; u < npw; ++u) user_of[sb.perm[u]] = u;
+  std::map<std::tuple<int, int, int>, int> where;   // Miller index -> internal index
+  for (int u = 0; u < npw; ++u) {
+    const int* m = d.miller + 3 * u;
+    where[std::make_tuple(m[0], m[1], m[2])] = sb.perm[u];
+  }
+  auto it0 = where.find(std::make_tuple(0, 0, 0));
+  if (it0 == where.end()) {
+    set_error("gamma_only: the sphere has no G = 0");
+    throw Error(STH_E_INVALID);
+  }
+  s.k0 = it0->second;
+  s.nmir = npw - 1 - s.k0;
+  if (2 * s.nmir + 1 != npw) {
+    set_error("gamma_only: G = 0 at internal index %d of %d: the sphere is not symmetric", s.k0,
+              npw);
+    throw Error(STH_E_INVALID);
+  }
+  std::vector<int> mir(s.nmir);
+  for (int i = 0; i < s.nmir; ++i) {
+    const int* m = d.miller + 3 * user_of[s.k0 + 1 + i];
+    auto it = where.find(std::make_tuple(-m[0], -m[1], -m[2]));
+    if (it == where.end() || it->second >= s.k0) {
+      set_error("gamma_only: -G of (%d, %d, %d) is missing or not before G = 0", m[0], m[1], m[2]);
+      throw Error(STH_E_INVALID);
+    }
+    mir[i] = it->second;
+  }
+  s.d_mirror = upload(&budget_, mir, st_);
+  DevMem out(&budget_, 2 * (size_t)s.M * sizeof(double));
+  launch_sym_check(s.d_W.as<z64>(), s.M, npw, s.k0, s.nmir, s.d_mirror.as<int>(),
+                   out.as<double>(), st_);
+  std::vector<double> h(2 * (size_t)s.M);
+  STH_HIP_CHECK(hipMemcpyAsync(h.data(), out.as<void>(), h.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, st_));
+  STH_HIP_CHECK(hipStreamSynchronize(st_));
+  for (int r = 0; r < s.M; ++r)
+    if (!(h[r] <= 1e-10 * h[s.M + r])) {
+      set_error("gamma_only: %s row %d is not real in real space (|W(-G) - conj W(G)| = %.3g, "
+                "largest |W| %.3g)", r < s.nv ? "psi_v" : "beta", r < s.nv ? r : r - s.nv, h[r],
+                h[s.M + r]);
+      throw Error(STH_E_INVALID);
+    }
+  s.gamma = true;
+}
+
+template <typename T>
+void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, double sgn,
+                         VecSet<const z64> in, VecSet<z64> out, const int* dl, int n, double s0,
+                         VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C) {
+  const int k0 = s.k0, Kh = s.npw - k0;
+  const double vb = double(Kh) * sizeof(z64), wb = double(Kh) * sizeof(cpx<T>);
+  const double gf = 8.0 * M * double(Kh) * n;
+  const int nsp = (Kh + s.kchunk - 1) / s.kchunk;
+  int h = prof_begin(PH_GEMM_AHB);
+  launch_gemm_ah_b(A + k0, s.npw, M, VecSet<const z64>{in.base + k0, in.stride}, dl, n, Kh,
+                   s.kchunk, part, st_);
+  prof_end(h, M * wb + n * vb, gf);
+  h = prof_begin(PH_REDUCE);
+  launch_reduce_parts_gamma<T, cpx<T>>(part, nsp, n, M, diag, sgn, C, A, s.npw, k0, in, dl, st_);
+  prof_end(h, (nsp + 1.0) * n * M * sizeof(cpx<T>), 0.0);
+  h = prof_begin(PH_GEMM_AC);
+  launch_gemm_a_c(A + k0, s.npw, M, C, VecSet<z64>{out.base + k0, out.stride}, dl, n, Kh, s0,
+                  {nullptr, 0}, nullptr, st_);
+  launch_mirror(out, dl, n, k0, s.nmir, s.d_mirror.as<int>(), st_);
+  if (dots)
+    launch_dots_tiles(dot_in, {out.base, out.stride}, dl, n, s.npw, s.ntile, dots, st_);
+  prof_end(h, M * wb + n * vb * 3.0 + (dots ? n * 2.0 * s.npw * sizeof(z64) : 0.0), gf);
+}
+template void Context::gamma_pair<double>(System&, const z64*, int, const double*, double,
+                                          VecSet<const z64>, VecSet<z64>, const int*, int, double,
+                                          VecSet<const z64>, double*, z64*, z64*);
+template void Context::gamma_pair<float>(System&, const z32*, int, const double*, double,
+                                         VecSet<const z64>, VecSet<z64>, const int*, int, double,
+                                         VecSet<const z64>, double*, z32*, z32*);
+
 // Geometry, potentials and W = [psi_v (nv rows, may be 0); beta] of a system on the device.
 StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) {
   s.N = d.n;
@@ -419,6 +504,7 @@ StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) 
     }
     STH_HIP_CHECK(hipStreamSynchronize(st_));
   }
+  if (d.gamma_only) setup_gamma(s, d, sb);
   std::vector<double> diag(s.M, 0.0);
   if (s.nproj) {
     std::vector<double> dij(s.nproj);
@@ -621,6 +707,12 @@ void Context::apply_op(System& s, VecSet<const z64> in, VecSet<z64> out, const i
   launch_zfft_fwd<double, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
                                s.ss.eps, st_);
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
+  if (s.gamma) {
+    gamma_pair<double>(s, s.beta(), M, dkb, 1.0, in, out, dl, n, 1.0, in,
+                       dots ? s.d_dots.as<double>() : nullptr, s.d_part.as<z64>(),
+                       s.d_C.as<z64>());
+    return;
+  }
   // the GEMM partials are indexed by list position; the slot list maps them back
   h = prof_begin(PH_GEMM_AHB);
   launch_gemm_ah_b(s.beta(), s.npw, M, in, dl, n, s.npw, s.kchunk, s.d_part.as<z64>(), st_);
@@ -661,6 +753,11 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
                               s.ss.eps, st_);
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
   h = prof_begin(PH_GEMM_AHB);
+  if (s.gamma && !bf16) {
+    gamma_pair<float>(s, w32, M, dkb, 1.0, in, out, dl, n, 1.0, in,
+                      dots ? s.d_dots.as<double>() : nullptr, part, C);
+    return;
+  }
   // the stick buffer is free once the forward z-FFTs have read it: it holds
   // the bf16 split of the vectors, then of C
   bz* split_scratch = reinterpret_cast<bz*>(s.d_sticks.as<z64>());
@@ -707,6 +804,16 @@ void Context::project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<c
   const double vb = double(s.npw) * sizeof(z64);
   const double gf = 8.0 * s.nv * double(s.npw) * n;
   double* dd = dots ? s.d_dots.as<double>() : nullptr;
+  if (s.gamma) {
+    if (mode == OP_FP64)
+      gamma_pair<double>(s, s.W(), s.nv, nullptr, -1.0, {v.base, v.stride}, v, dl, n, 1.0,
+                         dot_in, dd, s.d_part.as<z64>(), s.d_C.as<z64>());
+    else
+      gamma_pair<float>(s, s.d_W32.as<z32>(), s.nv, nullptr, -1.0, {v.base, v.stride}, v, dl, n,
+                        1.0, dot_in, dd, reinterpret_cast<z32*>(s.d_part.as<z64>()),
+                        reinterpret_cast<z32*>(s.d_C.as<z64>()));
+    return;
+  }
   int h = prof_begin(PH_GEMM_AHB);
   if (mode == OP_FP64) {
     launch_gemm_ah_b(s.W(), s.npw, s.nv, {v.base, v.stride}, dl, n, s.npw, s.kchunk,
@@ -1253,11 +1360,16 @@ void Context::refill(System& s) {
                              st_);
   launch_zfft_fwd<double, z64>(s.g, {sticks.base, sticks.stride}, s.vec(s.d_b), dl, n, ZF_PLAIN,
                                {nullptr, 0}, nullptr, st_);
+  if (s.gamma) {
+    gamma_pair<double>(s, s.W(), s.nv, nullptr, 1.0, s.cvec(s.d_b), s.vec(s.d_b), dl, n, -1.0,
+                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>());
+  } else {
   launch_gemm_ah_b(s.W(), s.npw, s.nv, s.cvec(s.d_b), dl, n, s.npw, s.kchunk, s.d_part.as<z64>(),
                    st_);
   launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.nv, nullptr, 1.0, s.d_C.as<z64>(), st_);
   launch_gemm_a_c(s.W(), s.npw, s.nv, s.d_C.as<z64>(), s.vec(s.d_b), dl, n, s.npw, -1.0,
                   {nullptr, 0}, nullptr, st_);
+  }
   launch_cg_init(s.g, s.cvec(s.d_b), s.vec(s.d_x), s.vec(s.d_r), s.vec(s.d_p), dl, n, s.ss.ekin,
                  s.d_part2.as<double>(), st_);
   launch_cg_init_scalars(s.d_part2.as<double>(), s.nchunk, dl, n, s.ss, st_);
@@ -1386,11 +1498,16 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
   const int n = int(fin.size());
   int* dl = upload_list(s, fin);
   // x <- P_c x, then store into the owning request's dpsi
+  if (s.gamma) {
+    gamma_pair<double>(s, s.W(), s.nv, nullptr, -1.0, s.cvec(s.d_x), s.vec(s.d_x), dl, n, 1.0,
+                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>());
+  } else {
   launch_gemm_ah_b(s.W(), s.npw, s.nv, s.cvec(s.d_x), dl, n, s.npw, s.kchunk, s.d_part.as<z64>(),
                    st_);
   launch_reduce_parts(s.d_part.as<z64>(), s.nsplit, n, s.nv, nullptr, -1.0, s.d_C.as<z64>(), st_);
   launch_gemm_a_c(s.W(), s.npw, s.nv, s.d_C.as<z64>(), s.vec(s.d_x), dl, n, s.npw, 1.0,
                   {nullptr, 0}, nullptr, st_);
+  }
   std::map<Request*, std::pair<std::vector<int>, std::vector<int>>> by_req;
   for (int slot : fin) {
     Request* r = s.slots[slot].req;

@@ -152,6 +152,11 @@ struct System {
   DevMem d_Wb;         // bf16 high and low planes of W, rows of bf16_ldw(npw) (STH_MIXED_BF16)
   DevMem d_vloc32;     // FP32 copy of V_loc
   DevMem d_psir;       // [nv][N^3] z64, psi_v(r) without Omega^{-1/2}
+  // Gamma-point systems: internal index k0 of G = 0, and for the nmir elements
+  // after it the internal index of -G (all before k0)
+  bool gamma = false;
+  int k0 = 0, nmir = 0;
+  DevMem d_mirror;
   DevMem d_eps_band;   // [nv]
   std::vector<double> eps, ekin;   // per band
   std::vector<int> perm;           // caller index -> internal index
@@ -279,6 +284,14 @@ class Context {
                   bool dots, bool bf16);
   // v <- P_c v on the listed slots (FP64 GEMMs for OP_FP64, FP32 otherwise);
   // with `dots`, partial Re<dot_in, v> per 64-row tile of the projected v into d_dots
+  void setup_gamma(System& s, const sth_system_desc& d, const StickBuild& sb);
+  // Projector product pair on half the sphere of a Gamma-point system:
+  // C = sgn diag (W^H in) (real), out = s0 out + W C, mirrored; with `dots`
+  // the tile partials of Re <dot_in, out> over the whole sphere
+  template <typename T>
+  void gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, double sgn,
+                  VecSet<const z64> in, VecSet<z64> out, const int* dl, int n, double s0,
+                  VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C);
   void project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
                  bool dots, int mode);
   void order_after(hipStream_t user);   // library stream waits for the user's stream

@@ -127,6 +127,22 @@ void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const 
                           VecSet<const z64> dot_in, double* dots, bz* scratch,
                           size_t scratch_bytes, hipStream_t st);
 
+// ---- Gamma-point half-sphere projector products (k_gamma.hip) ----
+// C[c][m] = sgn d_m (2 Re sum_s part[s][c][m] - Re(conj(W[m][k0]) X_c[k0])), imaginary part 0
+template <typename T, typename TW>
+void launch_reduce_parts_gamma(const cpx<T>* part, int nsplit, int ncols, int M,
+                               const double* diag, double sgn, cpx<T>* C, const TW* W, int ldw,
+                               int k0, VecSet<const z64> X, const int* slots, hipStream_t st);
+// Y[mirror[i]] = conj(Y[k0 + 1 + i]), i < nmir, and Im Y[k0] = 0 on the listed vectors
+void launch_mirror(VecSet<z64> Y, const int* slots, int ncols, int k0, int nmir,
+                   const int* mirror, hipStream_t st);
+// dots[c][t]: Re <a_c, b_c> over the 64-element tile t of the sphere (ntile tiles)
+void launch_dots_tiles(VecSet<const z64> a, VecSet<const z64> b, const int* slots, int ncols,
+                       int npw, int ntile, double* dots, hipStream_t st);
+// out[r]: largest |W_r(-G) - conj W_r(G)| over the half sphere; out[R + r]: largest |W_r|
+void launch_sym_check(const z64* W, int R, int npw, int k0, int nmir, const int* mirror,
+                      double* out, hipStream_t st);
+
 // ---- CG vector kernels (FP64) ----
 struct SlotState {
   double* rho;       // [nslots] <r, K r>

@@ -1,0 +1,111 @@
+"""GPU parity of the Gamma-point form (sth_system_desc.gamma_only): the
+projector products on half the sphere against the general complex form on the
+same real-in-real-space valence states (tests/gamma_util.py), and against the
+oracle.  Calls go through the C-ABI.
+
+* Config 1 (24^3): H.psi is unchanged (its products run on the whole sphere);
+  two perturbations x all 16 bands, FP64 at tolerance 1e-12: Delta psi and
+  Delta n of the Gamma-point system equal those of the complex system within
+  1e-10 and the oracle's LU solutions within 1e-10; STH_MIXED (FP32
+  projections on the half sphere) and STH_MIXED_BF16 at 1e-8 within 1e-6 of
+  the oracle.  A valence state with a complex phase is refused (STH_E_INVALID).
+* The 64-atom crystal (72^3): the oracle's valence states made symmetric, two
+  perturbations x all 128 bands in FP64: Delta psi and Delta n of the two forms
+  within 1e-10.
+"""
+import numpy as np
+import pytest
+
+import gamma_util
+import oracle
+import oracle_store
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(P, ctx, sid, dv, nv, prec, tol):
+    t = P.sth_submit_solves(ctx, sid, dv, np.arange(nv), tol=tol, precision=prec, want_dpsi=True)
+    assert P.sth_wait(ctx, t, 300.0)
+    npert = dv.shape[0]
+    info = P.sth_system_info_get(ctx, sid)
+    x = np.empty((npert, nv, info["npw"]), np.complex128)
+    P.sth_fetch_dpsi(ctx, t, x)
+    dn = np.empty((npert,) + (info["n"],) * 3)
+    P.sth_fetch_drho(ctx, t, dn)
+    iters, resid, status, _ = P.sth_fetch_stats(ctx, t, npert * nv)
+    P.sth_release_ticket(ctx, t)
+    print(f"precision {prec}: statuses {sorted(set(status.tolist()))} iters "
+          f"{iters.min()}..{iters.max()} max resid {resid.max():.3e}")
+    assert np.all(status == 0) and resid.max() <= tol
+    return x, dn
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_gamma_cfg1(cfg1_system, cfg1_dense):
+    import paper_2203_05623_amd as P
+    cfg = workloads.get_config("cfg1")
+    s = cfg1_system
+    H, w, V = cfg1_dense
+    nv = cfg.nv
+    eps, psi = gamma_util.realify(V[:nv], s.miller, lambda B: (H @ B.T).T)
+    mir = gamma_util.mirror_index(s.miller)
+    assert np.abs(psi[:, mir].conj() - psi).max() < 1e-13
+    dv = workloads.dv_block(cfg, range(2))
+    ref = np.array([[oracle.solve_lu(H, psi, eps[v], oracle.rhs(s, psi, v, dv[j]))
+                     for v in range(nv)] for j in range(2)])
+    ref_dn = np.stack([oracle.drho(s, psi, ref[j]) for j in range(2)])
+    ctx = P.sth_create(device=0, max_slots=64)
+    try:
+        sg = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps,
+                              gamma_only=True)
+        sc = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+        c = psi[:3] + 0.5 * psi[3:6]
+        h_g = P.sth_apply_h(ctx, sg, c)
+        assert _rel(h_g, oracle.apply_H(s, c)) < 1e-12
+        xg, dng = _solve(P, ctx, sg, dv, nv, P.STH_FP64, 1e-12)
+        xc, dnc = _solve(P, ctx, sc, dv, nv, P.STH_FP64, 1e-12)
+        e_gc, e_dn = _rel(xg, xc), _rel(dng, dnc)
+        e_x, e_n = _rel(xg, ref), _rel(dng, ref_dn)
+        print(f"cfg1 gamma FP64: vs complex form dpsi {e_gc:.2e} dn {e_dn:.2e}; "
+              f"vs oracle dpsi {e_x:.2e} dn {e_n:.2e}")
+        assert e_gc < 1e-10 and e_dn < 1e-10 and e_x < 1e-10 and e_n < 1e-10
+        for prec in (P.STH_MIXED, P.STH_MIXED_BF16):
+            xm, dnm = _solve(P, ctx, sg, dv, nv, prec, 1e-8)
+            e_x, e_n = _rel(xm, ref), _rel(dnm, ref_dn)
+            print(f"cfg1 gamma precision {prec}: vs oracle dpsi {e_x:.2e} dn {e_n:.2e}")
+            assert e_x < 1e-6 and e_n < 1e-6
+        bad = psi.copy()
+        bad[0] *= np.exp(0.3j)
+        with pytest.raises(P.SthError) as e:
+            P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, bad, eps,
+                             gamma_only=True)
+        assert e.value.code == P.STH_E_INVALID
+    finally:
+        P.sth_destroy(ctx)
+
+
+def test_gamma_cfg2():
+    import paper_2203_05623_amd as P
+    cfg = workloads.get_config("cfg2")
+    s = oracle.build_system("cfg2")
+    nv = cfg.nv
+    eps0, psi0 = oracle_store.valence("cfg2")
+    eps, psi = gamma_util.realify(psi0[:nv], s.miller, lambda B: oracle.apply_H(s, B))
+    assert np.abs(eps - eps0[:nv]).max() < 1e-9
+    dv = workloads.dv_block(cfg, range(2))
+    ctx = P.sth_create(device=0, max_slots=256)
+    try:
+        sg = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps,
+                              gamma_only=True)
+        sc = P.sth_set_system(ctx, cfg.L, cfg.N, s.miller, s.vloc_r, s.beta, s.dij, psi, eps)
+        xg, dng = _solve(P, ctx, sg, dv, nv, P.STH_FP64, 1e-12)
+        xc, dnc = _solve(P, ctx, sc, dv, nv, P.STH_FP64, 1e-12)
+        e_gc, e_dn = _rel(xg, xc), _rel(dng, dnc)
+        print(f"cfg2 gamma FP64 vs complex form: dpsi {e_gc:.2e} dn {e_dn:.2e}")
+        assert e_gc < 1e-10 and e_dn < 1e-10
+    finally:
+        P.sth_destroy(ctx)
