@@ -8,9 +8,12 @@ a 144^3 grid (187,511 plane waves, 1024 valence bands from the device
 eigensolver, 2048 KB projectors), 4 of its 64 perturbations per step = 4,096
 solves, in FP64 and (the `compare` object) BF16-mixed precision, timed alike;
 then the 64-atom crystal on a 72^3 grid (256 perturbations x 128 bands =
-32,768 solves per step) the same way (the `extra` object).
+32,768 solves per step) the same way (the `extra` object).  Both sample the
+Brillouin zone at Gamma as the paper's benchmarks do: the valence states are
+made real in real space (set-up, untimed) and the projector products run on
+half the sphere; --complex runs the general complex form instead.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5] [--npert 4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5] [--npert 4] [--complex]
 
 Prints one JSON line.  The CPU baseline is the oracle (plain FP64 NumPy PCG)
 timed on a bounded sample of the same solves by worker processes forked
@@ -402,6 +405,40 @@ def _roofline(prof, precision, nproj, nv, workload):
     return roof
 
 
+def _realify(P, torch, ctx, sid, miller, psi):
+    """Set-up of Gamma-point runs (not timed): an orthonormal basis of the
+    occupied space whose vectors are real in real space, c(-G) = conj c(G),
+    and H's eigenpairs in it.  The occupied space of a real Hamiltonian with a
+    gap above it is closed under c -> conj c(-G), so the symmetric and
+    antisymmetric parts of the given states span it; the nv largest
+    eigenvalues of their real Gram matrix pick the basis and a Rayleigh-Ritz
+    step on it (H applied by the library) the rotation.  Products run on the
+    GPU in FP64 (torch), the small eigenproblems on the host."""
+    nv = psi.shape[0]
+    dev = "cuda:0"
+    pos = {tuple(m): i for i, m in enumerate(miller.tolist())}
+    mir = torch.tensor([pos[(-a, -b, -c)] for a, b, c in miller.tolist()], device=dev)
+    ps = torch.from_numpy(np.ascontiguousarray(psi)).to(dev)
+    jp = ps[:, mir].conj()
+    S = torch.cat([(ps + jp) * 0.5, (ps - jp) * (-0.5j)])
+    del ps, jp
+    G = (S.conj() @ S.T.contiguous()).real.cpu().numpy()
+    w, U = np.linalg.eigh((G + G.T) / 2)
+    idx = np.argsort(w)[::-1]
+    if not (w[idx[nv - 1]] > 0.5 and w[idx[nv]] < 1e-6):
+        raise RuntimeError(f"occupied space not closed under c -> conj c(-G): Gram eigenvalues "
+                           f"{w[idx[nv - 1]]:.3e}, {w[idx[nv]]:.3e} around band {nv}")
+    R = torch.from_numpy(np.ascontiguousarray(U[:, idx[:nv]].T / np.sqrt(w[idx[:nv]])[:, None]))
+    B = R.to(dev, torch.complex128) @ S
+    del S
+    HB = P.sth_apply_h(ctx, sid, B)
+    Hs = (B.conj() @ HB.T.contiguous()).real.cpu().numpy()
+    del HB
+    e, V = np.linalg.eigh((Hs + Hs.T) / 2)
+    out = (torch.from_numpy(np.ascontiguousarray(V.T)).to(dev, torch.complex128) @ B).cpu()
+    return e, out.numpy()
+
+
 def run_workload(P, torch, name, npert, args, pool=None):
     """Valence set-up, resident system, then timed steps of every requested
     precision (profiling off, captured graphs on) and one profiled step of the
@@ -432,6 +469,22 @@ def run_workload(P, torch, name, npert, args, pool=None):
         t_sys = time.perf_counter() - t0
         if pool is not None:
             pool.set_valence(eps[:cfg.nv], psi[:cfg.nv])
+        t_real = None
+        gamma = not args.complex
+        if gamma:
+            # Gamma-point form: states real in real space, projector products on
+            # half the sphere
+            t0 = time.perf_counter()
+            eps_g, psi_g = _realify(P, torch, ctx, sid, miller, psi[:cfg.nv])
+            P.sth_release_system(ctx, sid)
+            t_real = time.perf_counter() - t0
+            print(f"{name}: Gamma-point states in {t_real:.1f} s (max |eps - eps_complex| "
+                  f"{np.abs(eps_g - eps[:cfg.nv]).max():.1e})", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            sid = P.sth_set_system(ctx, cfg.L, cfg.N, miller, vloc, beta, dij, psi_g, eps_g,
+                                   gamma_only=True)
+            t_sys = time.perf_counter() - t0
+            del psi_g
         del psi
         tinfo = P.sth_system_info_get(ctx, sid)
         tuning = {k: tinfo[k] for k in ("fft_plan_fp64", "plane_kernel_fp64", "zfft_kernel_fp64",
@@ -492,7 +545,8 @@ def run_workload(P, torch, name, npert, args, pool=None):
             torch.cuda.synchronize()
             prof = P.sth_profile_read(ctx)
             P.sth_profile(ctx, False)
-            roof = _roofline(prof, args.precision, beta.shape[0], cfg.nv, name)
+            roof = _roofline(prof, args.precision, beta.shape[0], cfg.nv,
+                             name + ("/gamma" if gamma else ""))
             phases = {k: {"ms": round(v[0], 3), "launches": v[1],
                           "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
                           "TFLOP/s": (round(v[3] / (v[0] * 1e-3) / 1e12, 2)
@@ -504,11 +558,13 @@ def run_workload(P, torch, name, npert, args, pool=None):
     desc = (f"{name}: {cfg.natoms}-atom synthetic crystal, {cfg.N}^3 grid, {len(miller)} plane "
             f"waves, {cfg.nv} bands, {beta.shape[0]} KB projectors; {npert} of the workload's "
             f"{cfg.npert} perturbations x {cfg.nv} bands = {nsolves} solves per step "
-            f"(+ Delta n and the chi0 block), tol {args.tol:g} true relative residual")
+            f"(+ Delta n and the chi0 block), tol {args.tol:g} true relative residual"
+            + (", Gamma-point states (half-sphere projector products)" if gamma else
+               ", general complex form"))
     return {"name": name, "desc": desc, "nsolves": nsolves, "legs": legs, "roofline": roof,
             "phases": phases, "tuning": tuning,
             "setup": {"valence_s": t_val, "valence_iters": vits, "valence_residual": vres,
-                      "gap_Ha": gap, "set_system_s": t_sys}}
+                      "gap_Ha": gap, "set_system_s": t_sys, "gamma_states_s": t_real}}
 
 
 def main():
@@ -526,6 +582,9 @@ def main():
     ap.add_argument("--extra", default="cfg2",
                     help="second workload timed the same way after the first (empty: skip)")
     ap.add_argument("--slots", type=int, default=2048)
+    ap.add_argument("--complex", action="store_true",
+                    help="general complex form (projector products over the whole sphere) "
+                         "instead of the Gamma-point form of the paper's benchmarks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle solves sampled (0: auto)")
     ap.add_argument("--cpu-maxit", type=int, default=0,

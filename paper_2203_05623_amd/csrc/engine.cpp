@@ -375,7 +375,8 @@ void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, 
                    s.kchunk, part, st_);
   prof_end(h, M * wb + n * vb, gf);
   h = prof_begin(PH_REDUCE);
-  launch_reduce_parts_gamma<T, cpx<T>>(part, nsp, n, M, diag, sgn, C, A, s.npw, k0, in, dl, st_);
+  launch_reduce_parts_gamma<T, cpx<T>>(part, nsp, n, M, diag, sgn, C, A, s.npw, k0, k0, in, dl,
+                                       st_);
   prof_end(h, (nsp + 1.0) * n * M * sizeof(cpx<T>), 0.0);
   h = prof_begin(PH_GEMM_AC);
   launch_gemm_a_c(A + k0, s.npw, M, C, VecSet<z64>{out.base + k0, out.stride}, dl, n, Kh, s0,
@@ -752,7 +753,6 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   launch_zfft_fwd<float, z64>(s.g, {sticks.base, sticks.stride}, out, dl, n, ZF_SHIFT, in,
                               s.ss.eps, st_);
   prof_end(h, n * (sb + 2.0 * vb) + s.npw * 8.0, 0.0);
-  h = prof_begin(PH_GEMM_AHB);
   if (s.gamma && !bf16) {
     gamma_pair<float>(s, w32, M, dkb, 1.0, in, out, dl, n, 1.0, in,
                       dots ? s.d_dots.as<double>() : nullptr, part, C);
@@ -762,9 +762,35 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   // the bf16 split of the vectors, then of C
   bz* split_scratch = reinterpret_cast<bz*>(s.d_sticks.as<z64>());
   const size_t split_bytes = s.d_sticks.bytes();
+  if (s.gamma) {
+    // half-sphere products from the 16-byte aligned column kh <= k0 on (the
+    // planes are read in 4-column chunks); the reduction removes the doubled
+    // columns [kh, k0)
+    const int kh = s.k0 & ~3, Kh = s.npw - kh;
+    const int nsp = (Kh + s.kchunk - 1) / s.kchunk;
+    const double vh = double(Kh) * sizeof(z64), gh = 8.0 * M * double(Kh) * n;
+    h = prof_begin(PH_GEMM_AHB);
+    launch_gemm_ah_b_bf16(wb, wplane, ldw, kh, M, {in.base + kh, in.stride}, dl, n, Kh,
+                          s.kchunk, part, split_scratch, split_bytes, st_);
+    prof_end(h, M * vh / 2 + n * vh, gh);
+    h = prof_begin(PH_REDUCE);
+    launch_reduce_parts_gamma<float, z32>(part, nsp, n, M, dkb, 1.0, C, w32, s.npw, s.k0, kh, in,
+                                          dl, st_);
+    prof_end(h, (nsp + 1.0) * n * M * sizeof(z32), 0.0);
+    h = prof_begin(PH_GEMM_AC);
+    launch_gemm_a_c_bf16(wb, wplane, ldw, kh, M, C, {out.base + kh, out.stride}, dl, n, Kh, 1.0,
+                         {nullptr, 0}, nullptr, split_scratch, split_bytes, st_);
+    launch_mirror(out, dl, n, s.k0, s.nmir, s.d_mirror.as<int>(), st_);
+    if (dots)
+      launch_dots_tiles(in, {out.base, out.stride}, dl, n, s.npw, s.ntile, s.d_dots.as<double>(),
+                        st_);
+    prof_end(h, M * vh / 2 + n * vh * 3.0 + (dots ? n * 2.0 * vb : 0.0), gh);
+    return;
+  }
+  h = prof_begin(PH_GEMM_AHB);
   if (bf16)
-    launch_gemm_ah_b_bf16(wb, wplane, ldw, M, in, dl, n, s.npw, s.kchunk, part, split_scratch,
-                          split_bytes, st_);
+    launch_gemm_ah_b_bf16(wb, wplane, ldw, 0, M, in, dl, n, s.npw, s.kchunk, part,
+                          split_scratch, split_bytes, st_);
   else
     launch_gemm_ah_b(w32, s.npw, M, in, dl, n, s.npw, s.kchunk, part, st_);
   prof_end(h, M * vb / 2 + n * vb, gf);
@@ -773,7 +799,7 @@ void Context::apply_op32(System& s, VecSet<const z64> in, VecSet<z64> out, const
   prof_end(h, (s.nsplit + 1.0) * n * M * sizeof(z32), 0.0);
   h = prof_begin(PH_GEMM_AC);
   if (bf16)
-    launch_gemm_a_c_bf16(wb, wplane, ldw, M, C, out, dl, n, s.npw, 1.0, in,
+    launch_gemm_a_c_bf16(wb, wplane, ldw, 0, M, C, out, dl, n, s.npw, 1.0, in,
                          dots ? s.d_dots.as<double>() : nullptr, split_scratch, split_bytes,
                          st_);
   else

@@ -17,21 +17,25 @@ namespace sth {
 
 namespace {
 
-// C[c][m] = sgn d_m (2 Re sum_s part[s][c][m] - Re(conj(W[m][k0]) x_c[k0])), real
+// C[c][m] = sgn d_m (2 Re sum_s part[s][c][m] - Re(conj(W[m][k0]) x_c[k0])
+//                    - 2 Re sum_{kh <= k < k0} conj(W[m][k]) x_c[k]), real
 template <typename T, typename TW>
 __global__ void k_reduce_parts_gamma(const cpx<T>* part, int nsplit, int ncols, int M,
                                      const double* diag, double sgn, cpx<T>* C, const TW* W,
-                                     int ldw, int k0, VecSet<const z64> X, const int* slots) {
+                                     int ldw, int k0, int kh, VecSet<const z64> X,
+                                     const int* slots) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)ncols * M) return;
   const int c = int(i / M), m = int(i - (long long)c * M);
   double re = 0.0;
   for (int s = 0; s < nsplit; ++s) re += part[(long long)s * ncols * M + i].x;
-  const TW w = W[(long long)m * ldw + k0];
-  const z64 x = X.base[(long long)slots[c] * X.stride + k0];
-  const double g0 = double(w.x) * x.x + double(w.y) * x.y;
+  const TW* w = W + (long long)m * ldw;
+  const z64* x = X.base + (long long)slots[c] * X.stride;
+  double extra = 0.0;
+  for (int k = kh; k < k0; ++k) extra += double(w[k].x) * x[k].x + double(w[k].y) * x[k].y;
+  const double g0 = double(w[k0].x) * x[k0].x + double(w[k0].y) * x[k0].y;
   const double d = sgn * (diag ? diag[m] : 1.0);
-  C[i] = cpx<T>{T(d * (2.0 * re - g0)), T(0)};
+  C[i] = cpx<T>{T(d * (2.0 * (re - extra) - g0)), T(0)};
 }
 
 // Y[mirror[i]] = conj(Y[k0 + 1 + i]) and Im Y[k0] = 0 for every listed vector:
@@ -100,18 +104,23 @@ __global__ __launch_bounds__(256) void k_sym_check(const TW* W, int R, int npw, 
 template <typename T, typename TW>
 void launch_reduce_parts_gamma(const cpx<T>* part, int nsplit, int ncols, int M,
                                const double* diag, double sgn, cpx<T>* C, const TW* W, int ldw,
-                               int k0, VecSet<const z64> X, const int* slots, hipStream_t st) {
+                               int k0, int kh, VecSet<const z64> X, const int* slots,
+                               hipStream_t st) {
   const long long n = (long long)ncols * M;
   if (n <= 0) return;
+  if (kh > k0 || kh < 0) {
+    set_error("gamma reduction: half start %d after G = 0 at %d", kh, k0);
+    throw Error(STH_E_INTERNAL);
+  }
   hipLaunchKernelGGL((k_reduce_parts_gamma<T, TW>), dim3((unsigned)((n + 255) / 256)), dim3(256),
-                     0, st, part, nsplit, ncols, M, diag, sgn, C, W, ldw, k0, X, slots);
+                     0, st, part, nsplit, ncols, M, diag, sgn, C, W, ldw, k0, kh, X, slots);
   STH_HIP_CHECK(hipGetLastError());
 }
 template void launch_reduce_parts_gamma<double, z64>(const z64*, int, int, int, const double*,
-                                                     double, z64*, const z64*, int, int,
+                                                     double, z64*, const z64*, int, int, int,
                                                      VecSet<const z64>, const int*, hipStream_t);
 template void launch_reduce_parts_gamma<float, z32>(const z32*, int, int, int, const double*,
-                                                    double, z32*, const z32*, int, int,
+                                                    double, z32*, const z32*, int, int, int,
                                                     VecSet<const z64>, const int*, hipStream_t);
 
 void launch_mirror(VecSet<z64> Y, const int* slots, int ncols, int k0, int nmir,

@@ -14,6 +14,7 @@
 // v_mfma_f32_16x16x32_bf16 lane layout (64 lanes, l = lane), measured on gfx950:
 //   A[i][k]: i = l % 16, k = 8 (l / 16) + e (e < 8 bf16 values per lane);
 //   B[k][j]: k = 8 (l / 16) + e, j = l % 16;  D[i][j], register v: i = 4 (l / 16) + v, j = l % 16.
+#include <algorithm>
 #include <cstdlib>
 
 #include "errors.hpp"
@@ -376,16 +377,26 @@ int bf16_tile() {
   return t;
 }
 
-void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
-                           const int* slots, int ncols, int K, int kchunk, z32* part,
-                           bz* scratch, size_t scratch_bytes, hipStream_t st) {
+// the rows of W hold the columns [koff, koff + K) and every column the last
+// tiles read past them (whole 64-column tiles of Y += W C, whole 32-column
+// stages of C = W^H B)
+static bool bf16_cols_fit(int ldw, int koff, int K) {
+  return ldw % 64 == 0 && koff >= 0 && koff % 4 == 0 &&
+         koff + std::max(((K + 63) / 64) * 64, K + 31) <= ldw;
+}
+
+void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int koff, int M,
+                           VecSet<const z64> B, const int* slots, int ncols, int K, int kchunk,
+                           z32* part, bz* scratch, size_t scratch_bytes, hipStream_t st) {
   if (ncols <= 0 || M <= 0) return;
   const long long pplane = (long long)ncols * ldw;
-  if (ldw != bf16_ldw(K) || kchunk % 4 != 0 || size_t(2 * pplane) * sizeof(bz) > scratch_bytes) {
-    set_error("bf16 GEMM: row pitch %d (want %d), K chunk %d (multiple of 4), scratch %zu B",
-              ldw, bf16_ldw(K), kchunk, scratch_bytes);
+  if (!bf16_cols_fit(ldw, koff, K) || kchunk % 4 != 0 ||
+      size_t(2 * pplane) * sizeof(bz) > scratch_bytes) {
+    set_error("bf16 GEMM: row pitch %d, columns [%d, %d + %d), K chunk %d (multiple of 4), "
+              "scratch %zu B", ldw, koff, koff, K, kchunk, scratch_bytes);
     throw Error(STH_E_INTERNAL);
   }
+  Wb += koff;
   hipLaunchKernelGGL(k_split_cols, dim3((unsigned)((ldw + 255) / 256), (unsigned)ncols),
                      dim3(256), 0, st, B, slots, K, ldw, scratch, pplane);
   const int nsplit = (K + kchunk - 1) / kchunk;
@@ -401,18 +412,19 @@ void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSe
   STH_HIP_CHECK(hipGetLastError());
 }
 
-void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const z32* C,
+void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int koff, int M, const z32* C,
                           VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
                           VecSet<const z64> dot_in, double* dots, bz* scratch,
                           size_t scratch_bytes, hipStream_t st) {
   if (ncols <= 0) return;
   const int Mp = ((M + BK - 1) / BK) * BK;
   const long long cplane = (long long)ncols * Mp;
-  if (ldw != bf16_ldw(K) || size_t(2 * cplane) * sizeof(bz) > scratch_bytes) {
-    set_error("bf16 GEMM: row pitch %d (want %d), scratch %zu B", ldw, bf16_ldw(K),
-              scratch_bytes);
+  if (!bf16_cols_fit(ldw, koff, K) || size_t(2 * cplane) * sizeof(bz) > scratch_bytes) {
+    set_error("bf16 GEMM: row pitch %d, columns [%d, %d + %d), scratch %zu B", ldw, koff, koff,
+              K, scratch_bytes);
     throw Error(STH_E_INTERNAL);
   }
+  Wb += koff;
   if (Mp > 0)
     hipLaunchKernelGGL(k_split_c, dim3((unsigned)((Mp + 255) / 256), (unsigned)ncols),
                        dim3(256), 0, st, C, M, Mp, scratch, cplane);

@@ -116,23 +116,30 @@ struct bz {
 inline int bf16_ldw(int K) { return ((K + 63) / 64) * 64 + 64; }
 void launch_split_w(const z32* W, int M, int K, int ldw, bz* Wb, hipStream_t st);
 // Wb: the hi plane of the rows used; the lo plane starts wplane elements later.
+// The product runs over the K columns from column koff of those rows (koff a
+// multiple of 4, koff + max(K rounded up to 64, K + 31) <= ldw: the reads of
+// the last tiles stay in the row); B and Y are given at that column.
 // scratch (scratch_bytes): device memory free for the call, where the vectors
 // (2 ncols ldw bz) or C (2 ncols Mp bz, Mp = M rounded up to 32) are split
 // into bf16 hi/lo planes once before the product.
-void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int M, VecSet<const z64> B,
-                           const int* slots, int ncols, int K, int kchunk, z32* part,
-                           bz* scratch, size_t scratch_bytes, hipStream_t st);
-void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int M, const z32* C,
+void launch_gemm_ah_b_bf16(const bz* Wb, long long wplane, int ldw, int koff, int M,
+                           VecSet<const z64> B, const int* slots, int ncols, int K, int kchunk,
+                           z32* part, bz* scratch, size_t scratch_bytes, hipStream_t st);
+void launch_gemm_a_c_bf16(const bz* Wb, long long wplane, int ldw, int koff, int M, const z32* C,
                           VecSet<z64> Y, const int* slots, int ncols, int K, double s0,
                           VecSet<const z64> dot_in, double* dots, bz* scratch,
                           size_t scratch_bytes, hipStream_t st);
 
 // ---- Gamma-point half-sphere projector products (k_gamma.hip) ----
-// C[c][m] = sgn d_m (2 Re sum_s part[s][c][m] - Re(conj(W[m][k0]) X_c[k0])), imaginary part 0
+// C[c][m] = sgn d_m (2 Re sum_s part[s][c][m] - Re(conj(W[m][k0]) X_c[k0])
+//                    - 2 Re sum_{kh <= k < k0} conj(W[m][k]) X_c[k]), imaginary part 0:
+// the partial sums cover the columns from kh <= k0 on (an aligned start takes
+// up to three mirrored columns before G = 0, counted twice by the 2 Re)
 template <typename T, typename TW>
 void launch_reduce_parts_gamma(const cpx<T>* part, int nsplit, int ncols, int M,
                                const double* diag, double sgn, cpx<T>* C, const TW* W, int ldw,
-                               int k0, VecSet<const z64> X, const int* slots, hipStream_t st);
+                               int k0, int kh, VecSet<const z64> X, const int* slots,
+                               hipStream_t st);
 // Y[mirror[i]] = conj(Y[k0 + 1 + i]), i < nmir, and Im Y[k0] = 0 on the listed vectors
 void launch_mirror(VecSet<z64> Y, const int* slots, int ncols, int k0, int nmir,
                    const int* mirror, hipStream_t st);

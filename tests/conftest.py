@@ -27,3 +27,12 @@ def cfg1_dense(cfg1_system):
     H = oracle.dense_H(cfg1_system)
     w, V = np.linalg.eigh(H)
     return H, w, np.ascontiguousarray(V.T)
+
+
+@pytest.fixture(scope="session")
+def oracle_systems():
+    """Oracle systems by name, each built once per session (the 144^3 one, with
+    its 2048 projectors over 187,511 plane waves, takes about a minute)."""
+    import functools
+    import oracle
+    return functools.lru_cache(maxsize=3)(oracle.build_system)

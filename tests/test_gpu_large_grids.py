@@ -20,8 +20,6 @@ Calls go through the C-ABI.
   a many-band valence set at 96^3 and 144^3 is checked on free-electron closed
   shells in test_gpu_closed_shell.py.)
 """
-import functools
-
 import numpy as np
 import pytest
 
@@ -41,11 +39,6 @@ def sth():
     P.sth_destroy(ctx)
 
 
-@functools.lru_cache(maxsize=2)
-def _system(name):
-    return oracle.build_system(name)
-
-
 def _orthonormal_rows(npw, nv, seed):
     """nv orthonormal vectors (any orthonormal set serves H.psi, which ignores them)."""
     rng = np.random.default_rng(seed)
@@ -55,10 +48,10 @@ def _orthonormal_rows(npw, nv, seed):
 
 @pytest.mark.parametrize("kind", [2, 4])
 @pytest.mark.parametrize("name", ["cfg4c", "cfg5"])
-def test_apply_h_large_grid(sth, name, kind, monkeypatch, tmp_path):
+def test_apply_h_large_grid(sth, oracle_systems, name, kind, monkeypatch, tmp_path):
     P, ctx = sth
     cfg = workloads.get_config(name)
-    s = _system(name)
+    s = oracle_systems(name)
     psi = _orthonormal_rows(s.npw, 4, 3)
     eps = np.arange(4.0)
     info = tune_force.shape_info(P, ctx, cfg, s, psi, eps)
@@ -80,12 +73,12 @@ def test_apply_h_large_grid(sth, name, kind, monkeypatch, tmp_path):
 
 
 @pytest.mark.parametrize("kind", [2, 4])
-def test_solves_144_lowest_band(sth, kind, monkeypatch, tmp_path):
+def test_solves_144_lowest_band(sth, oracle_systems, kind, monkeypatch, tmp_path):
     P, ctx = sth
     cfg = workloads.get_config("cfg5")
     eps, psi = oracle_store.valence("cfg5", nv=1)
     r = oracle_store.load("cfg5", "response", nv=1)
-    s = _system("cfg5")
+    s = oracle_systems("cfg5")
     psi, eps = np.ascontiguousarray(psi[:1]), eps[:1]
     ref_x = r["dpsi"]
     ref_dn = np.stack([oracle.drho(s, psi, ref_x[j][None]) for j in range(ref_x.shape[0])])
