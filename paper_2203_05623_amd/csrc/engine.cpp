@@ -365,20 +365,23 @@ void Context::setup_gamma(System& s, const sth_system_desc& d, const StickBuild&
 template <typename T>
 void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, double sgn,
                          VecSet<const z64> in, VecSet<z64> out, const int* dl, int n, double s0,
-                         VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C) {
+                         VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C,
+                         bool phases) {
   const int k0 = s.k0, Kh = s.npw - k0;
   const double vb = double(Kh) * sizeof(z64), wb = double(Kh) * sizeof(cpx<T>);
   const double gf = 8.0 * M * double(Kh) * n;
   const int nsp = (Kh + s.kchunk - 1) / s.kchunk;
-  int h = prof_begin(PH_GEMM_AHB);
+  // phases == false: the caller books the launches under a phase of its own
+  auto begin = [&](int phase) { return phases ? prof_begin(phase) : -1; };
+  int h = begin(PH_GEMM_AHB);
   launch_gemm_ah_b(A + k0, s.npw, M, VecSet<const z64>{in.base + k0, in.stride}, dl, n, Kh,
                    s.kchunk, part, st_);
   prof_end(h, M * wb + n * vb, gf);
-  h = prof_begin(PH_REDUCE);
+  h = begin(PH_REDUCE);
   launch_reduce_parts_gamma<T, cpx<T>>(part, nsp, n, M, diag, sgn, C, A, s.npw, k0, k0, in, dl,
                                        st_);
   prof_end(h, (nsp + 1.0) * n * M * sizeof(cpx<T>), 0.0);
-  h = prof_begin(PH_GEMM_AC);
+  h = begin(PH_GEMM_AC);
   launch_gemm_a_c(A + k0, s.npw, M, C, VecSet<z64>{out.base + k0, out.stride}, dl, n, Kh, s0,
                   {nullptr, 0}, nullptr, st_);
   launch_mirror(out, dl, n, k0, s.nmir, s.d_mirror.as<int>(), st_);
@@ -388,10 +391,10 @@ void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, 
 }
 template void Context::gamma_pair<double>(System&, const z64*, int, const double*, double,
                                           VecSet<const z64>, VecSet<z64>, const int*, int, double,
-                                          VecSet<const z64>, double*, z64*, z64*);
+                                          VecSet<const z64>, double*, z64*, z64*, bool);
 template void Context::gamma_pair<float>(System&, const z32*, int, const double*, double,
                                          VecSet<const z64>, VecSet<z64>, const int*, int, double,
-                                         VecSet<const z64>, double*, z32*, z32*);
+                                         VecSet<const z64>, double*, z32*, z32*, bool);
 
 // Geometry, potentials and W = [psi_v (nv rows, may be 0); beta] of a system on the device.
 StickBuild Context::setup_geometry(System& s, const sth_system_desc& d, int nv) {
@@ -1388,7 +1391,7 @@ void Context::refill(System& s) {
                                {nullptr, 0}, nullptr, st_);
   if (s.gamma) {
     gamma_pair<double>(s, s.W(), s.nv, nullptr, 1.0, s.cvec(s.d_b), s.vec(s.d_b), dl, n, -1.0,
-                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>());
+                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>(), false);
   } else {
   launch_gemm_ah_b(s.W(), s.npw, s.nv, s.cvec(s.d_b), dl, n, s.npw, s.kchunk, s.d_part.as<z64>(),
                    st_);
@@ -1526,7 +1529,7 @@ void Context::check_and_retire(System& s, std::vector<int>& act) {
   // x <- P_c x, then store into the owning request's dpsi
   if (s.gamma) {
     gamma_pair<double>(s, s.W(), s.nv, nullptr, -1.0, s.cvec(s.d_x), s.vec(s.d_x), dl, n, 1.0,
-                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>());
+                       {nullptr, 0}, nullptr, s.d_part.as<z64>(), s.d_C.as<z64>(), false);
   } else {
   launch_gemm_ah_b(s.W(), s.npw, s.nv, s.cvec(s.d_x), dl, n, s.npw, s.kchunk, s.d_part.as<z64>(),
                    st_);

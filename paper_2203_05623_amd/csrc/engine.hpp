@@ -287,11 +287,13 @@ class Context {
   void setup_gamma(System& s, const sth_system_desc& d, const StickBuild& sb);
   // Projector product pair on half the sphere of a Gamma-point system:
   // C = sgn diag (W^H in) (real), out = s0 out + W C, mirrored; with `dots`
-  // the tile partials of Re <dot_in, out> over the whole sphere
+  // the tile partials of Re <dot_in, out> over the whole sphere; `phases`
+  // books the launches under the GEMM and reduction phases of the profiler
   template <typename T>
   void gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, double sgn,
                   VecSet<const z64> in, VecSet<z64> out, const int* dl, int n, double s0,
-                  VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C);
+                  VecSet<const z64> dot_in, double* dots, cpx<T>* part, cpx<T>* C,
+                  bool phases = true);
   void project_c(System& s, VecSet<z64> v, const int* dl, int n, VecSet<const z64> dot_in,
                  bool dots, int mode);
   void order_after(hipStream_t user);   // library stream waits for the user's stream
