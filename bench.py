@@ -51,9 +51,7 @@ HBM_OVER_ALGORITHMIC = {
     # 72^3 single-pass plane kernels (persistent form FP64, workgroup form FP32)
     ("cfg2", "plane", "fp64"): 1.005, ("cfg2", "plane", "mixed-bf16"): 1.009,
     ("cfg2", "gemm_ah_b", "fp64"): 1.852,
-    # Gamma-point form: half-sphere projector GEMMs (algorithmic bytes over the
-    # half); the plane kernels are those of the complex form
-    ("cfg5/gamma", "gemm_ah_b", "fp64"): 4.510,
+    # Gamma-point form: the plane kernels are those of the complex form
     ("cfg5/gamma", "plane", "fp64"): 1.909, ("cfg5/gamma", "plane", "mixed-bf16"): 1.327,
     ("cfg2/gamma", "plane", "fp64"): 1.005, ("cfg2/gamma", "plane", "mixed-bf16"): 1.009,
 }

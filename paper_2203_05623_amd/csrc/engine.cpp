@@ -369,13 +369,14 @@ void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, 
                          bool phases) {
   const int k0 = s.k0, Kh = s.npw - k0;
   const double vb = double(Kh) * sizeof(z64), wb = double(Kh) * sizeof(cpx<T>);
-  const double gf = 8.0 * M * double(Kh) * n;
+  const double gf = 4.0 * M * double(Kh) * n;   // real products over the half sphere
   const int nsp = (Kh + s.kchunk - 1) / s.kchunk;
   // phases == false: the caller books the launches under a phase of its own
   auto begin = [&](int phase) { return phases ? prof_begin(phase) : -1; };
   int h = begin(PH_GEMM_AHB);
+  // the projections are real: only Re conj(W) x is formed, and Y += W C takes C real
   launch_gemm_ah_b(A + k0, s.npw, M, VecSet<const z64>{in.base + k0, in.stride}, dl, n, Kh,
-                   s.kchunk, part, st_);
+                   s.kchunk, part, st_, true);
   prof_end(h, M * wb + n * vb, gf);
   h = begin(PH_REDUCE);
   launch_reduce_parts_gamma<T, cpx<T>>(part, nsp, n, M, diag, sgn, C, A, s.npw, k0, k0, in, dl,
@@ -383,7 +384,7 @@ void Context::gamma_pair(System& s, const cpx<T>* A, int M, const double* diag, 
   prof_end(h, (nsp + 1.0) * n * M * sizeof(cpx<T>), 0.0);
   h = begin(PH_GEMM_AC);
   launch_gemm_a_c(A + k0, s.npw, M, C, VecSet<z64>{out.base + k0, out.stride}, dl, n, Kh, s0,
-                  {nullptr, 0}, nullptr, st_);
+                  {nullptr, 0}, nullptr, st_, true);
   launch_mirror(out, dl, n, k0, s.nmir, s.d_mirror.as<int>(), st_);
   if (dots)
     launch_dots_tiles(dot_in, {out.base, out.stride}, dl, n, s.npw, s.ntile, dots, st_);

@@ -61,7 +61,10 @@ constexpr int gemm_wpe() { return sizeof(T) == 8 ? 3 : 4; }
 // Workgroup tile: 64 rows of A x 32 NY columns of B; the 4 waves sit 2 x 2, each
 // holding 32 rows x 16 NY columns (2 x NY MFMA tiles, real and imaginary parts).
 // NY = 4 (128 columns) halves the re-reads of A per column of B against NY = 2.
-template <typename T, typename TB, int NY>
+// RE: only the real part, Re conj(A) B = A.x B.x + A.y B.y (imaginary part
+// written as 0), half the products: the form of Gamma-point systems, whose
+// projections are real.
+template <typename T, typename TB, int NY, bool RE = false>
 __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? gemm_wpe<T>() : 2))) void k_gemm_ah_b(const cpx<T>* __restrict__ A, int lda, int M,
                                                     VecSet<const TB> B, const int* slots,
                                                     int ncols, int K, int kchunk, cpx<T>* part) {
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? 
 #pragma unroll
         for (int y = 0; y < NY; ++y) {
           accr[x][y] = Mfma<T>::op(a[x], br[y], accr[x][y]);
-          acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
+          if constexpr (!RE) acci[x][y] = Mfma<T>::op(a[x], bi[y], acci[x][y]);
         }
     }
     __syncthreads();
@@ -155,7 +158,8 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? 
         const int m = m0 + wm * 32 + x * 16 + Mfma<T>::row(kq, v);
         const int n = n0 + wn * 16 * NY + y * 16 + r16;
         if (m < M && n < ncols)
-          part[((long long)s * ncols + n) * M + m] = cpx<T>{accr[x][y][v], acci[x][y][v]};
+          part[((long long)s * ncols + n) * M + m] =
+              cpx<T>{accr[x][y][v], RE ? T(0) : acci[x][y][v]};
       }
 }
 
@@ -183,7 +187,10 @@ __global__ void k_reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M,
 // Workgroup tile: 64 rows g x 32 NY columns; each wave 32 g x 16 NY columns.
 // The FP64 register budget for three workgroups per CU measured 55 TFLOP/s
 // against 48 with the compiler's two-workgroup default.
-template <typename T, int NY>
+// RE: C real (its imaginary part is not read), Y.x += sum A.x C and
+// Y.y += sum A.y C: each MFMA k-step covers 4 rows m instead of 2, half the
+// products (Gamma-point systems).
+template <typename T, int NY, bool RE = false>
 __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? gemm_wpe<T>() : 2))) void k_gemm_a_c(
     const cpx<T>* __restrict__ A, int lda, int M, const cpx<T>* __restrict__ C, VecSet<z64> Y,
     const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots) {
@@ -238,6 +245,36 @@ __global__ __launch_bounds__(GTHR) __attribute__((amdgpu_waves_per_eu(NY == 2 ? 
     }
     __syncthreads();
     if (mb + GK < M) fetch(mb + GK);
+    if constexpr (RE) {
+      // MFMA k slot kq holds row m = 4 kk + kq
+#pragma unroll
+      for (int kk = 0; kk < GK / 4; ++kk) {
+        const int mm = 4 * kk + kq;
+        T ar[2], ai[2], b[NY];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const cpx<T> w = Ws[mm][wg * 32 + t * 16 + r16];
+          ar[t] = w.x;
+          ai[t] = w.y;
+        }
+#pragma unroll
+        for (int t = 0; t < NY; ++t) b[t] = Cs[wn * 16 * NY + t * 16 + r16][mm].x;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < NY; ++y) {
+            if constexpr (sizeof(T) == 4) {   // transposed tile, as below
+              accr[x][y] = Mfma<T>::op(b[y], ar[x], accr[x][y]);
+              acci[x][y] = Mfma<T>::op(b[y], ai[x], acci[x][y]);
+            } else {
+              accr[x][y] = Mfma<T>::op(ar[x], b[y], accr[x][y]);
+              acci[x][y] = Mfma<T>::op(ai[x], b[y], acci[x][y]);
+            }
+          }
+      }
+      __syncthreads();
+      continue;
+    }
 #pragma unroll
     for (int kk = 0; kk < GK / 2; ++kk) {
       const int mm = 2 * kk + (kq >> 1);
@@ -392,18 +429,18 @@ int gemm_ny() {
   return ny;
 }
 
-template <typename T>
+template <typename T, bool RE>
 void gemm_ah_b(const cpx<T>* A, int lda, int M, VecSet<const z64> B, const int* slots, int ncols,
                int K, int kchunk, cpx<T>* part, hipStream_t st) {
   if (ncols <= 0 || M <= 0) return;
   const int nsplit = (K + kchunk - 1) / kchunk;
   if (gemm_ny() == 4 && ncols >= 256) {
     dim3 grid((M + GT - 1) / GT, (ncols + 127) / 128, nsplit);
-    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 4>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
+    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 4, RE>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
                        ncols, K, kchunk, part);
   } else {
     dim3 grid((M + GT - 1) / GT, (ncols + GT - 1) / GT, nsplit);
-    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 2>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
+    hipLaunchKernelGGL((k_gemm_ah_b<T, z64, 2, RE>), grid, dim3(GTHR), 0, st, A, lda, M, B, slots,
                        ncols, K, kchunk, part);
   }
   STH_HIP_CHECK(hipGetLastError());
@@ -419,19 +456,19 @@ void reduce_parts(const cpx<T>* part, int nsplit, int ncols, int M, const double
   STH_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, bool RE>
 void gemm_a_c(const cpx<T>* A, int lda, int M, const cpx<T>* C, VecSet<z64> Y, const int* slots,
               int ncols, int K, double s0, VecSet<const z64> dot_in, double* dots,
               hipStream_t st) {
   if (ncols <= 0) return;
   if (gemm_ny() == 4 && ncols >= 256) {
     dim3 grid(gemm_a_c_tiles(K), (ncols + 127) / 128);
-    hipLaunchKernelGGL((k_gemm_a_c<T, 4>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols,
-                       K, s0, dot_in, dots);
+    hipLaunchKernelGGL((k_gemm_a_c<T, 4, RE>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots,
+                       ncols, K, s0, dot_in, dots);
   } else {
     dim3 grid(gemm_a_c_tiles(K), (ncols + GT - 1) / GT);
-    hipLaunchKernelGGL((k_gemm_a_c<T, 2>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots, ncols,
-                       K, s0, dot_in, dots);
+    hipLaunchKernelGGL((k_gemm_a_c<T, 2, RE>), grid, dim3(GTHR), 0, st, A, lda, M, C, Y, slots,
+                       ncols, K, s0, dot_in, dots);
   }
   STH_HIP_CHECK(hipGetLastError());
 }
@@ -439,12 +476,18 @@ void gemm_a_c(const cpx<T>* A, int lda, int M, const cpx<T>* C, VecSet<z64> Y, c
 }  // namespace
 
 void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
-                      int ncols, int K, int kchunk, z64* part, hipStream_t st) {
-  gemm_ah_b<double>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
+                      int ncols, int K, int kchunk, z64* part, hipStream_t st, bool real) {
+  if (real)
+    gemm_ah_b<double, true>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
+  else
+    gemm_ah_b<double, false>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
 }
 void launch_gemm_ah_b(const z32* A, int lda, int M, VecSet<const z64> B, const int* slots,
-                      int ncols, int K, int kchunk, z32* part, hipStream_t st) {
-  gemm_ah_b<float>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
+                      int ncols, int K, int kchunk, z32* part, hipStream_t st, bool real) {
+  if (real)
+    gemm_ah_b<float, true>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
+  else
+    gemm_ah_b<float, false>(A, lda, M, B, slots, ncols, K, kchunk, part, st);
 }
 
 void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
@@ -458,13 +501,19 @@ void launch_reduce_parts(const z32* part, int nsplit, int ncols, int M, const do
 
 void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
-                     double* dots, hipStream_t st) {
-  gemm_a_c<double>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
+                     double* dots, hipStream_t st, bool real) {
+  if (real)
+    gemm_a_c<double, true>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
+  else
+    gemm_a_c<double, false>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
 }
 void launch_gemm_a_c(const z32* A, int lda, int M, const z32* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
-                     double* dots, hipStream_t st) {
-  gemm_a_c<float>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
+                     double* dots, hipStream_t st, bool real) {
+  if (real)
+    gemm_a_c<float, true>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
+  else
+    gemm_a_c<float, false>(A, lda, M, C, Y, slots, ncols, K, s0, dot_in, dots, st);
 }
 
 }  // namespace sth

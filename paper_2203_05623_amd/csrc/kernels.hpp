@@ -83,26 +83,30 @@ constexpr int kTileMaxN = 96;        // largest grid whose N x (N + 1) FP64 plan
 constexpr int kStageSlots = 1024;    // strip-form persistent workgroups (up to four per CU)
 
 // ---- dense contractions on MFMA (FP64) ----
-// part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda)
+// part[s][c][m] = sum_{k in split s} conj(A[m][k]) * B_c[k]     (A rows of length lda);
+// real: only its real part (imaginary part 0), half the MFMA work
 void launch_gemm_ah_b(const z64* A, int lda, int M, VecSet<const z64> B, const int* slots,
-                      int ncols, int K, int kchunk, z64* part, hipStream_t st);
+                      int ncols, int K, int kchunk, z64* part, hipStream_t st,
+                      bool real = false);
 // C[c][m] = sgn * diag[m] * sum_s part[s][c][m]   (diag may be null -> 1);
 // transpose: written as C[m][c] instead (row m = <A_m| . >, a Gram matrix row)
 void launch_reduce_parts(const z64* part, int nsplit, int ncols, int M, const double* diag,
                          double sgn, z64* C, hipStream_t st, bool transpose = false);
 // Y_c[g] = s0 * Y_c[g] + sum_m A[m][g] C[c][m]; if dot_in, also
 // dots[c][tile] = sum_{g in tile} Re(conj(dot_in_c[g]) Y_c[g]) for 64-wide tiles of g.
+// real: C is real (its imaginary part is not read), half the MFMA work
 void launch_gemm_a_c(const z64* A, int lda, int M, const z64* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
-                     double* dots, hipStream_t st);
+                     double* dots, hipStream_t st, bool real = false);
 // FP32 variants (W and C in FP32, FP32 MFMA accumulation; B, Y, dots FP64 in memory)
 void launch_gemm_ah_b(const z32* A, int lda, int M, VecSet<const z64> B, const int* slots,
-                      int ncols, int K, int kchunk, z32* part, hipStream_t st);
+                      int ncols, int K, int kchunk, z32* part, hipStream_t st,
+                      bool real = false);
 void launch_reduce_parts(const z32* part, int nsplit, int ncols, int M, const double* diag,
                          double sgn, z32* C, hipStream_t st, bool transpose = false);
 void launch_gemm_a_c(const z32* A, int lda, int M, const z32* C, VecSet<z64> Y,
                      const int* slots, int ncols, int K, double s0, VecSet<const z64> dot_in,
-                     double* dots, hipStream_t st);
+                     double* dots, hipStream_t st, bool real = false);
 void launch_z64_to_z32(const z64* src, z32* dst, long long n, hipStream_t st);
 inline int gemm_a_c_tiles(int K) { return (K + 63) / 64; }
 
