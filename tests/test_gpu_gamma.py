@@ -4,7 +4,7 @@ same real-in-real-space valence states (tests/gamma_util.py), and against the
 oracle.  Calls go through the C-ABI.
 
 * Config 1 (24^3): H.psi is unchanged (its products run on the whole sphere);
-  two perturbations x all 16 bands, FP64 at tolerance 1e-12: Delta psi and
+  two perturbations x all 8 bands, FP64 at tolerance 1e-12: Delta psi and
   Delta n of the Gamma-point system equal those of the complex system within
   1e-10 and the oracle's LU solutions within 1e-10; STH_MIXED (FP32
   projections on the half sphere) and STH_MIXED_BF16 at 1e-8 within 1e-6 of
@@ -16,8 +16,9 @@ oracle.  Calls go through the C-ABI.
   tuned kernels of that size: the oracle's lowest band made symmetric, its
   stored perturbations in FP64 at 1e-12 (the two forms within 1e-10; against
   the oracle's PCG solutions, rotated by the state's phase, within 1e-7: the
-  oracle state is symmetric only to 4e-10, its LOBPCG residual, and the
-  symmetrised state moves the solution by about that much), STH_MIXED and
+  oracle state, from an LOBPCG run stopped at residual 3e-9, is symmetric only
+  to 4e-10, and symmetrising it moves the solution by about that much),
+  STH_MIXED and
   STH_MIXED_BF16 at 1e-8 within 1e-6 of the FP64 complex form.
 """
 import numpy as np
