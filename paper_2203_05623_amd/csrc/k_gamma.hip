@@ -5,9 +5,10 @@
 //   C = 2 Re sum_{G in H} conj(W(G)) x(G) - Re(conj(W(0)) x(0)),
 // with H the half of the sphere that follows G = 0 in the internal (stick-major)
 // order, G = 0 included; Y += W C needs only the half H, the rest is
-// Y(-G) = conj Y(G).  The GEMM kernels run unchanged on the half (pointer
-// offsets); these kernels do the reduction with the G = 0 correction, the
-// mirror copy and the <a, b> tile partials over the whole sphere.
+// Y(-G) = conj Y(G).  The GEMM kernels run on the half through pointer
+// offsets, the FP64 / FP32 ones as real products (only Re conj(W) x, and C
+// taken as real); these kernels do the reduction with the G = 0 correction,
+// the mirror copy and the <a, b> tile partials over the whole sphere.
 #include <algorithm>
 
 #include "errors.hpp"
